@@ -1,0 +1,95 @@
+"""Seeded synthetic grayscale images: the shared input of the codec and its oracle.
+
+This module holds no part of the codec's arithmetic.  It stands in for the
+paper's photographic test images (Lena and Cable-car, Sec. 4), which are not
+available, with images of the same sizes and a similar mix of smooth shading,
+oriented texture at several scales, and sensor-like noise.
+
+Generator G(W, H, seed, sigma), NumPy ``default_rng(seed)`` (PCG64), draws in
+this order:
+
+1. for k = 1..6: period P_k = exp(U[ln 4, ln 128]), angle theta_k ~ U[0, pi),
+   phase phi_k ~ U[0, 2 pi), amplitude A_k ~ U[10, 30];
+2. gradient g_x, g_y ~ U[-40, 40];
+3. noise N(0, sigma^2) over the H x W grid, drawn row-major in bands of
+   ``_BAND`` rows.
+
+    I(x, y) = 128 + sum_k A_k sin(2 pi (x cos theta_k + y sin theta_k) / P_k + phi_k)
+                  + g_x (x / W - 1/2) + g_y (y / H - 1/2) + noise
+
+rounded half to even (``rint``), clipped to [0, 255], stored as uint8.  Each
+sinusoid is evaluated as sin(a x) cos(b y + phi) + cos(a x) sin(b y + phi) so
+that the cost is O(W + H) transcendentals plus a few multiply-adds per pixel;
+that evaluation order is part of the definition, and golden SHA-256 digests in
+the tests pin the bytes.
+"""
+import hashlib
+
+import numpy as np
+
+_BAND = 256
+
+
+def synth_image(W: int, H: int, seed: int, sigma: float = 5.0) -> np.ndarray:
+    """One (H, W) uint8 image from generator G."""
+    if W < 1 or H < 1:
+        raise ValueError("W and H must be positive")
+    rng = np.random.default_rng(seed)
+    per, ang, pha, amp = [], [], [], []
+    for _ in range(6):
+        per.append(np.exp(rng.uniform(np.log(4.0), np.log(128.0))))
+        ang.append(rng.uniform(0.0, np.pi))
+        pha.append(rng.uniform(0.0, 2.0 * np.pi))
+        amp.append(rng.uniform(10.0, 30.0))
+    gx = rng.uniform(-40.0, 40.0)
+    gy = rng.uniform(-40.0, 40.0)
+
+    x = np.arange(W, dtype=np.float64)
+    sx, cx = [], []
+    for k in range(6):
+        a = 2.0 * np.pi * np.cos(ang[k]) / per[k]
+        sx.append(amp[k] * np.sin(a * x))
+        cx.append(amp[k] * np.cos(a * x))
+    ramp_x = gx * (x / W - 0.5)
+
+    out = np.empty((H, W), np.uint8)
+    for y0 in range(0, H, _BAND):
+        y1 = min(H, y0 + _BAND)
+        y = np.arange(y0, y1, dtype=np.float64)
+        acc = np.empty((y1 - y0, W), np.float64)
+        acc[...] = 128.0 + ramp_x[None, :] + (gy * (y / H - 0.5))[:, None]
+        for k in range(6):
+            b = 2.0 * np.pi * np.sin(ang[k]) * y / per[k] + pha[k]
+            acc += np.cos(b)[:, None] * sx[k][None, :]
+            acc += np.sin(b)[:, None] * cx[k][None, :]
+        if sigma > 0:
+            acc += rng.normal(0.0, sigma, size=(y1 - y0, W))
+        np.rint(acc, out=acc)
+        np.clip(acc, 0.0, 255.0, out=acc)
+        out[y0:y1] = acc.astype(np.uint8)
+    return out
+
+
+def sigma_for_seed(seed: int) -> float:
+    """Noise level of the 8192 x 8192 workload: sigma = 2 + 8 s / 7 for s = 0..7."""
+    return 2.0 + 8.0 * (seed % 8) / 7.0
+
+
+def digest(img: np.ndarray) -> str:
+    """SHA-256 of the image bytes together with its shape."""
+    h = hashlib.sha256()
+    h.update(np.asarray(img.shape, np.int64).tobytes())
+    h.update(np.ascontiguousarray(img).tobytes())
+    return h.hexdigest()
+
+
+def pad_plane(img: np.ndarray, stride: int, fill: int = 0xA5) -> np.ndarray:
+    """Copy img into rows of ``stride`` bytes (stride >= W); returns the (H, W)
+    view of the padded buffer.  The pad bytes hold ``fill`` so a reader that
+    strays into them is noticed."""
+    H, W = img.shape
+    if stride < W:
+        raise ValueError("stride < W")
+    buf = np.full((H, stride), fill, np.uint8)
+    buf[:, :W] = img
+    return buf[:, :W]
