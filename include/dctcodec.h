@@ -1,0 +1,135 @@
+/*
+ * dctcodec.h -- C ABI of the blockwise 8x8 Cordic-based Loeffler DCT image codec
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The codec follows Modieginyane, Ncube and Gasela, "CUDA based performance
+ * evaluation of the computational efficiency of the DCT image compression
+ * technique on both the CPU and GPU":
+ *   - the transform is the 2-D DCT-II of Sec. 2.5.1, eq. (6)-(7) (orthonormal
+ *     scaling), on 8x8 blocks, computed as row then column 8-point Loeffler
+ *     flow graphs (Sec. 2.5.2) whose rotation blocks are fixed-point CORDIC
+ *     shift-add rotations;
+ *   - the DCT, the quantizer and the IDCT are separate stages (Sec. 3.2);
+ *   - reconstruction quality is PSNR, eq. (23)-(24) (Sec. 4.1).
+ *
+ * Integer recipe R(n, F, P) = R(10, 12, 15), identical bit for bit on every
+ * entry point:
+ *   samples      x = (p - 128) << F                      (level shift)
+ *   rotation     n micro-rotations a' = a + d_i (b >> i), b' = b - d_i (a >> i)
+ *                (simultaneous, arithmetic shifts), then a <- (a M + 2^(P-1)) >> P
+ *                per output; d_i from the greedy CORDIC rule, M = round(k 2^P / K_n)
+ *   forward      row pass then column pass; coefficient = c / 2^(F+3)  (Q16.15)
+ *   quantize     Q[u][v] = 1 + (1 + u + v) qs;
+ *                q = sgn(c) floor((|c| + Q 2^(F+2)) / (Q 2^(F+3))), saturated to int16
+ *   dequantize   clamp(q Q, -2048, 2047) << F
+ *   inverse      transposed graph (rotations by -theta), column pass then row pass
+ *   reconstruct  clamp(((x + 2^(F+2)) >> (F+3)) + 128, 0, 255)
+ * dct_recipe_info / dct_recipe_tables report the parameters and constants.
+ *
+ * Conventions shared by every entry point:
+ *   - Planes are uint8 grayscale, row-major, W x H pixels, rows `stride` bytes
+ *     apart.  stride >= W and stride % 8 == 0; the plane pointer is 8-byte
+ *     aligned.  A source plane must hold (H - 1) * stride + W readable bytes; the
+ *     library reads no byte outside the W x H region.  A destination plane gets
+ *     exactly its W x H region written; pad bytes are left untouched.
+ *   - The block grid is ceil(W/8) x ceil(H/8).  Pixels of edge blocks that lie
+ *     outside the image repeat the nearest pixel of the last column / row.
+ *   - Coefficient arrays are [nblocks][64]: blocks in row-major block order
+ *     (by * ceil(W/8) + bx), each block in natural (not zig-zag) order u * 8 + v
+ *     with u the vertical and v the horizontal frequency.  They are 16-byte
+ *     aligned.
+ *   - Pointers are device pointers unless marked "host".  The caller allocates
+ *     and owns every buffer; the library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *     enqueue their kernels on it and return without waiting unless stated.
+ *   - Sizes: 1 <= W, H <= 65535; 1 <= qs <= 1024.
+ *   - Every call returns a dct_status.  Arguments are checked before anything is
+ *     enqueued (DCT_ERR_INVALID); a failed launch gives DCT_ERR_DEVICE.  The
+ *     library never aborts and never throws across this interface.
+ *   - Thread safety: calls on different streams may run concurrently, except
+ *     dct_psnr, which serialises on a library lock (it uses a per-device scratch
+ *     word and waits for its stream).
+ */
+#ifndef DCTCODEC_H
+#define DCTCODEC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DCT_OK = 0,
+  DCT_ERR_INVALID = -1,     /* an argument violates the preconditions above */
+  DCT_ERR_UNSUPPORTED = -2, /* no gfx950 device is current */
+  DCT_ERR_DEVICE = -3,      /* the HIP runtime reported an error */
+  DCT_ERR_NOMEM = -4        /* the library could not allocate its scratch word */
+} dct_status;
+
+/* Forward transform, steps a1-a4 (level shift, row pass, transpose, column pass):
+ * the Loeffler flow graph of Sec. 2.5.2 with CORDIC rotation blocks, applied to
+ * every 8x8 block (2-D DCT-II of Sec. 2.5.1, eq. (6)).
+ *   src   W x H uint8 plane, row pitch src_stride.
+ *   coef  out: int32 [ceil(H/8) * ceil(W/8)][64]; coefficient = value / 2^15. */
+int dct_forward(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t *coef,
+                void *stream);
+
+/* Table quantizer, step a5 (the quantizer stage of Sec. 3.2).
+ *   coef     int32 [nblocks][64] as written by dct_forward (any int32 accepted).
+ *   nblocks  number of blocks, >= 0 (0 enqueues nothing).
+ *   qs       quality scale of the table Q[u][v] = 1 + (1 + u + v) qs.
+ *   qcoef    out: int16 [nblocks][64], nearest integer to coefficient / Q with
+ *            ties away from zero, saturated to [-32768, 32767]. */
+int dct_quantize(const int32_t *coef, int64_t nblocks, int32_t qs, int16_t *qcoef, void *stream);
+
+/* Dequantize and inverse transform, steps a6-a8 (the IDCT stage of Sec. 3.2; the
+ * inverse of eq. (6) named in Sec. 2.5.1).  Any int16 input is accepted: the
+ * dequantized value is clamped to [-2048, 2047] before the inverse.
+ *   qcoef  int16 [ceil(H/8) * ceil(W/8)][64].
+ *   qs     the quality scale the values were quantized with.
+ *   dst    out: W x H uint8 plane, row pitch dst_stride. */
+int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, uint8_t *dst,
+                int32_t dst_stride, void *stream);
+
+/* PSNR of plane b against plane a, step a9 (Sec. 4.1, eq. (23)-(24)).
+ *   peak       MAX of eq. (23): > 0 uses that value; 0 uses the largest pixel of a.
+ *   psnr_host  host out: 20 log10(MAX / sqrt(SSE / (W H))); +inf when SSE = 0.
+ *   sse_host   host out, may be NULL: the exact sum of squared differences.
+ * Waits for `stream` before returning. */
+int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W,
+             int32_t H, double peak, double *psnr_host, uint64_t *sse_host, void *stream);
+
+/* The whole codec in one pass, steps a1-a9: forward, quantize, dequantize,
+ * inverse, reconstruct, and the SSE of the reconstruction against the source.
+ * Bit-identical to dct_forward + dct_quantize + dct_inverse + dct_psnr.
+ *   dst            out: W x H uint8 reconstruction, row pitch dst_stride.
+ *   qcoef_or_null  out, optional: the int16 quantized values, as dct_quantize.
+ *   sse_dev        out: one uint64 in device memory, overwritten with the SSE
+ *                  (PSNR = 10 log10(255^2 W H / SSE)). */
+int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+              int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
+
+/* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
+ * the samples, fractional bits P of the gain constants. */
+int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits);
+
+/* Recipe constants (host outs), derived by the library at compile time:
+ *   directions  3 * n values in {-1, +1}: the CORDIC directions d_i of the
+ *               pi/16, 3pi/16 and 6pi/16 rotation blocks, in that order;
+ *   gains       4 values: M(pi/16), M(3pi/16), M(6pi/16) (including the sqrt(2)
+ *               of the even rotation), and round(sqrt(2) 2^P). */
+int dct_recipe_tables(int32_t *directions, int32_t *gains);
+
+/* Human-readable name of a dct_status value (static storage). */
+const char *dct_status_string(int status);
+
+/* Releases the library's per-device scratch words.  Optional; later calls
+ * allocate them again. */
+int dct_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCTCODEC_H */

@@ -433,13 +433,18 @@ int64_t or_cordic_forward(const uint8_t *src, int W, int H, int stride, int32_t 
   return peak;
 }
 
-/* a5: int32 coefficients -> int16 quantized values, same layout */
+/* a5: int32 coefficients -> int16 quantized values, same layout.  The int16
+ * container saturates; coefficients of a uint8 plane give |q| <= 1024 and never
+ * reach the limits, only arbitrary int32 input can. */
 void or_cordic_quantize(const int32_t *coef, int64_t nblocks, int qs, int16_t *qcoef) {
   for (int64_t b = 0; b < nblocks; ++b)
     for (int u = 0; u < 8; ++u)
       for (int v = 0; v < 8; ++v) {
         const int64_t k = b * 64 + u * 8 + v;
-        qcoef[k] = (int16_t)recipe_quantize(coef[k], qtable(u, v, qs));
+        int64_t q = recipe_quantize(coef[k], qtable(u, v, qs));
+        if (q > 32767) q = 32767;
+        if (q < -32768) q = -32768;
+        qcoef[k] = (int16_t)q;
       }
 }
 

@@ -264,3 +264,16 @@ def test_reconstruct_rounding(oracle_mod):
             x = k * S + delta
             p = math.floor(Fraction(x, S) + Fraction(1, 2)) + 128
             assert oracle_mod.recipe_reconstruct(x) == min(255, max(0, p))
+
+
+def test_quantize_saturates_to_int16(oracle_mod):
+    # arbitrary int32 coefficients: the int16 container saturates at its limits.
+    # qs = 1: Q[0][0] = 2, so c = 2^31 - 1 rounds to 32768 -> 32767 and c = -2^31
+    # gives exactly -32768; Q[0][1] = 3 gives 21845 with no saturation.
+    coef = np.zeros((2, 64), np.int32)
+    coef[0, 0] = 2 ** 31 - 1
+    coef[1, 0] = -(2 ** 31)
+    coef[0, 1] = 2 ** 31 - 1
+    q = oracle_mod.cordic_quantize(coef, 1)
+    assert q[0, 0] == 32767 and q[1, 0] == -32768 and q[0, 1] == 21845
+    assert not np.any(q[0, 2:]) and not np.any(q[1, 1:])
