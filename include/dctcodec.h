@@ -55,6 +55,12 @@
 
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define DCT_API __attribute__((visibility("default")))
+#else
+#define DCT_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -72,7 +78,7 @@ typedef enum {
  * every 8x8 block (2-D DCT-II of Sec. 2.5.1, eq. (6)).
  *   src   W x H uint8 plane, row pitch src_stride.
  *   coef  out: int32 [ceil(H/8) * ceil(W/8)][64]; coefficient = value / 2^15. */
-int dct_forward(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t *coef,
+DCT_API int dct_forward(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t *coef,
                 void *stream);
 
 /* Table quantizer, step a5 (the quantizer stage of Sec. 3.2).
@@ -81,7 +87,7 @@ int dct_forward(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, in
  *   qs       quality scale of the table Q[u][v] = 1 + (1 + u + v) qs.
  *   qcoef    out: int16 [nblocks][64], nearest integer to coefficient / Q with
  *            ties away from zero, saturated to [-32768, 32767]. */
-int dct_quantize(const int32_t *coef, int64_t nblocks, int32_t qs, int16_t *qcoef, void *stream);
+DCT_API int dct_quantize(const int32_t *coef, int64_t nblocks, int32_t qs, int16_t *qcoef, void *stream);
 
 /* Dequantize and inverse transform, steps a6-a8 (the IDCT stage of Sec. 3.2; the
  * inverse of eq. (6) named in Sec. 2.5.1).  Any int16 input is accepted: the
@@ -89,7 +95,7 @@ int dct_quantize(const int32_t *coef, int64_t nblocks, int32_t qs, int16_t *qcoe
  *   qcoef  int16 [ceil(H/8) * ceil(W/8)][64].
  *   qs     the quality scale the values were quantized with.
  *   dst    out: W x H uint8 plane, row pitch dst_stride. */
-int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, uint8_t *dst,
+DCT_API int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, uint8_t *dst,
                 int32_t dst_stride, void *stream);
 
 /* PSNR of plane b against plane a, step a9 (Sec. 4.1, eq. (23)-(24)).
@@ -97,7 +103,7 @@ int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, uint8_t 
  *   psnr_host  host out: 20 log10(MAX / sqrt(SSE / (W H))); +inf when SSE = 0.
  *   sse_host   host out, may be NULL: the exact sum of squared differences.
  * Waits for `stream` before returning. */
-int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W,
+DCT_API int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W,
              int32_t H, double peak, double *psnr_host, uint64_t *sse_host, void *stream);
 
 /* The whole codec in one pass, steps a1-a9: forward, quantize, dequantize,
@@ -107,26 +113,26 @@ int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_str
  *   qcoef_or_null  out, optional: the int16 quantized values, as dct_quantize.
  *   sse_dev        out: one uint64 in device memory, overwritten with the SSE
  *                  (PSNR = 10 log10(255^2 W H / SSE)). */
-int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+DCT_API int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
               int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
 
 /* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
  * the samples, fractional bits P of the gain constants. */
-int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits);
+DCT_API int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits);
 
 /* Recipe constants (host outs), derived by the library at compile time:
  *   directions  3 * n values in {-1, +1}: the CORDIC directions d_i of the
  *               pi/16, 3pi/16 and 6pi/16 rotation blocks, in that order;
  *   gains       4 values: M(pi/16), M(3pi/16), M(6pi/16) (including the sqrt(2)
  *               of the even rotation), and round(sqrt(2) 2^P). */
-int dct_recipe_tables(int32_t *directions, int32_t *gains);
+DCT_API int dct_recipe_tables(int32_t *directions, int32_t *gains);
 
 /* Human-readable name of a dct_status value (static storage). */
-const char *dct_status_string(int status);
+DCT_API const char *dct_status_string(int status);
 
 /* Releases the library's per-device scratch words.  Optional; later calls
  * allocate them again. */
-int dct_shutdown(void);
+DCT_API int dct_shutdown(void);
 
 #ifdef __cplusplus
 }

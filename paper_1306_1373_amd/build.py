@@ -1,0 +1,47 @@
+"""Build the HIP library libdctcodec.so for gfx950 in-tree.
+
+    python -m paper_1306_1373_amd.build [-v]
+
+The result goes to paper_1306_1373_amd/lib/libdctcodec.so.  Packed FP32
+instructions are disabled for all device code.
+"""
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB_DIR = os.path.join(PKG, "lib")
+LIB = os.path.join(LIB_DIR, "libdctcodec.so")
+SOURCES = [os.path.join(CSRC, "dctcodec.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp")] + [
+    os.path.join(INCLUDE, "dctcodec.h")]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-shared",
+    "-Wall", "-Wextra", "-Wno-unused-parameter",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-fvisibility=hidden",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+    "-Wl,-soname,libdctcodec.so",
+]
+
+
+def build(verbose: bool = False, extra=None, out: str = LIB) -> str:
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, *(extra or []), *SOURCES, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,224 @@
+"""Python binding of the C ABI in include/dctcodec.h.
+
+Argument marshalling only: each function checks tensor dtypes, shapes and
+devices, allocates missing outputs with torch (device memory is torch's), and
+passes raw pointers and the current HIP stream to the library.  Every step of
+the codec runs in the library's HIP kernels; there is no fallback path, and a
+missing or unloadable library raises.
+
+Planes are 2-D uint8 CUDA (HIP) tensors of shape (H, W) whose rows are
+contiguous (``stride(1) == 1``); a row pitch larger than W (a column slice of
+a wider buffer) is passed through as the plane's stride.
+"""
+import ctypes as C
+import os
+
+from . import build as _build
+
+_lib = None
+
+DCT_OK = 0
+DCT_ERR_INVALID = -1
+DCT_ERR_UNSUPPORTED = -2
+DCT_ERR_DEVICE = -3
+DCT_ERR_NOMEM = -4
+
+# prototypes of include/dctcodec.h
+_PROTOS = {
+    "dct_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dct_quantize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dct_inverse": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                              C.c_void_p]),
+    "dct_psnr": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                           C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_void_p]),
+    "dct_codec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                            C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
+    "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "dct_status_string": (C.c_char_p, [C.c_int]),
+    "dct_shutdown": (C.c_int, []),
+}
+
+
+class DctError(RuntimeError):
+    """A dct_* call returned a status other than DCT_OK."""
+
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = load().dct_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def library_path() -> str:
+    return os.environ.get("DCTCODEC_LIB", _build.LIB)
+
+
+def load() -> C.CDLL:
+    """Load libdctcodec.so (built by ``python -m paper_1306_1373_amd.build``).
+
+    torch is imported first so that the HIP runtime the library links against
+    is the one torch already loaded (both use the soname libamdhip64.so.7)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime first)
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run python -m paper_1306_1373_amd.build")
+    L = C.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != DCT_OK:
+        raise DctError(status, where)
+
+
+def _stream(t) -> int:
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _plane(t, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D uint8 tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.stride(1) != 1:
+        raise TypeError(f"{name} rows must be contiguous")
+    H, W = t.shape
+    stride = t.stride(0) if H > 1 else max(W, ((W + 7) // 8) * 8)
+    return t.data_ptr(), int(W), int(H), int(stride)
+
+
+def grid(W: int, H: int):
+    """(blocks per row, block rows) of a W x H image."""
+    return (W + 7) // 8, (H + 7) // 8
+
+
+def nblocks(W: int, H: int) -> int:
+    bw, bh = grid(W, H)
+    return bw * bh
+
+
+def new_plane(W: int, H: int, device, stride: int = None):
+    """A (H, W) uint8 device plane whose rows are ``stride`` bytes apart
+    (default: W rounded up to a multiple of 8)."""
+    import torch
+    stride = stride or ((W + 7) // 8) * 8
+    buf = torch.empty((H, stride), dtype=torch.uint8, device=device)
+    return buf[:, :W]
+
+
+def dct_forward(src, coef=None):
+    """a1-a4: int32 coefficients [nblocks, 64] of a uint8 plane (value / 2^15)."""
+    import torch
+    p, W, H, s = _plane(src, "src")
+    nb = nblocks(W, H)
+    if coef is None:
+        coef = torch.empty((nb, 64), dtype=torch.int32, device=src.device)
+    if coef.dtype != torch.int32 or not coef.is_contiguous() or coef.numel() != nb * 64:
+        raise TypeError("coef must be a contiguous int32 tensor of nblocks * 64 elements")
+    _check(load().dct_forward(p, W, H, s, coef.data_ptr(), _stream(src)), "dct_forward")
+    return coef
+
+
+def dct_quantize(coef, qs: int, qcoef=None):
+    """a5: int16 quantized values of int32 coefficients, table Q = 1 + (1 + u + v) qs."""
+    import torch
+    if coef.dtype != torch.int32 or not coef.is_contiguous() or coef.numel() % 64:
+        raise TypeError("coef must be a contiguous int32 tensor of whole blocks")
+    nb = coef.numel() // 64
+    if qcoef is None:
+        qcoef = torch.empty((nb, 64), dtype=torch.int16, device=coef.device)
+    if qcoef.dtype != torch.int16 or not qcoef.is_contiguous() or qcoef.numel() != nb * 64:
+        raise TypeError("qcoef must be a contiguous int16 tensor of nblocks * 64 elements")
+    _check(load().dct_quantize(coef.data_ptr(), nb, int(qs), qcoef.data_ptr(), _stream(coef)),
+           "dct_quantize")
+    return qcoef
+
+
+def dct_inverse(qcoef, qs: int, W: int, H: int, dst=None):
+    """a6-a8: W x H uint8 reconstruction of int16 quantized values."""
+    import torch
+    if qcoef.dtype != torch.int16 or not qcoef.is_contiguous() or qcoef.numel() != nblocks(W, H) * 64:
+        raise TypeError("qcoef must be a contiguous int16 tensor matching the block grid")
+    if dst is None:
+        dst = new_plane(W, H, qcoef.device)
+    p, dW, dH, s = _plane(dst, "dst")
+    if (dW, dH) != (W, H):
+        raise ValueError("dst shape does not match W, H")
+    _check(load().dct_inverse(qcoef.data_ptr(), int(qs), W, H, p, s, _stream(qcoef)), "dct_inverse")
+    return dst
+
+
+def dct_psnr(a, b, peak: float = 255.0):
+    """(psnr, sse) of plane b against plane a (waits for the stream)."""
+    pa, W, H, sa = _plane(a, "a")
+    pb, W2, H2, sb = _plane(b, "b")
+    if (W, H) != (W2, H2):
+        raise ValueError("planes differ in shape")
+    out = C.c_double()
+    sse = C.c_uint64()
+    _check(load().dct_psnr(pa, sa, pb, sb, W, H, float(peak), C.byref(out), C.byref(sse),
+                           _stream(a)), "dct_psnr")
+    return out.value, int(sse.value)
+
+
+def dct_codec(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
+    """a1-a9 in one pass.  Returns (dst, sse_tensor) or (dst, sse_tensor, qcoef);
+    sse_tensor is a one-element int64 device tensor holding the uint64 SSE."""
+    import torch
+    p, W, H, s = _plane(src, "src")
+    if dst is None:
+        dst = new_plane(W, H, src.device)
+    pd, dW, dH, ds = _plane(dst, "dst")
+    if (dW, dH) != (W, H):
+        raise ValueError("dst shape does not match src")
+    if want_qcoef and qcoef is None:
+        qcoef = torch.empty((nblocks(W, H), 64), dtype=torch.int16, device=src.device)
+    if qcoef is not None and (qcoef.dtype != torch.int16 or not qcoef.is_contiguous()
+                              or qcoef.numel() != nblocks(W, H) * 64):
+        raise TypeError("qcoef must be a contiguous int16 tensor matching the block grid")
+    if sse is None:
+        sse = torch.empty(1, dtype=torch.int64, device=src.device)
+    _check(load().dct_codec(p, W, H, s, int(qs), pd, ds,
+                            None if qcoef is None else qcoef.data_ptr(), sse.data_ptr(),
+                            _stream(src)), "dct_codec")
+    return (dst, sse, qcoef) if qcoef is not None else (dst, sse)
+
+
+def psnr_from_sse(sse: int, W: int, H: int, peak: float = 255.0) -> float:
+    """Host arithmetic of eq. (23) for an SSE returned by dct_codec."""
+    import math
+    if sse == 0:
+        return math.inf
+    return 10.0 * math.log10(peak * peak * W * H / sse)
+
+
+def recipe_info():
+    n, f, p = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().dct_recipe_info(C.byref(n), C.byref(f), C.byref(p)), "dct_recipe_info")
+    return n.value, f.value, p.value
+
+
+def recipe_tables():
+    n = recipe_info()[0]
+    d = (C.c_int32 * (3 * n))()
+    g = (C.c_int32 * 4)()
+    _check(load().dct_recipe_tables(d, g), "dct_recipe_tables")
+    return [[d[r * n + i] for i in range(n)] for r in range(3)], list(g)
+
+
+def status_string(status: int) -> str:
+    return load().dct_status_string(status).decode()
+
+
+def shutdown():
+    _check(load().dct_shutdown(), "dct_shutdown")

@@ -1,0 +1,211 @@
+// dctcodec.hip -- the C ABI of include/dctcodec.h: argument checks, quantizer
+// constants, launch shapes, and error mapping.  The kernels are in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <mutex>
+
+#include "dctcodec.h"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr int kMaxDim = 65535;
+constexpr int kMaxQs = 1024;
+
+std::mutex g_lock;                                   // guards the scratch table and dct_psnr
+std::array<unsigned long long *, kMaxDevices> g_scratch{};  // per device: {sse, max pixel}
+std::array<int, kMaxDevices> g_arch_ok{};            // 0 unknown, 1 gfx950, -1 other
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+bool plane_ok(const void *p, int32_t W, int32_t H, int32_t stride) {
+  return p != nullptr && aligned(p, 8) && W >= 1 && W <= kMaxDim && H >= 1 && H <= kMaxDim &&
+         stride >= W && stride % 8 == 0;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// The current device must be a gfx950 part.
+int check_device(int *dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DCT_ERR_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return DCT_ERR_UNSUPPORTED;
+  int ok = __atomic_load_n(&g_arch_ok[dev], __ATOMIC_ACQUIRE);
+  if (ok == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DCT_ERR_DEVICE;
+    ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    __atomic_store_n(&g_arch_ok[dev], ok, __ATOMIC_RELEASE);
+  }
+  if (ok < 0) return DCT_ERR_UNSUPPORTED;
+  if (dev_out) *dev_out = dev;
+  return DCT_OK;
+}
+
+int launched() { return hipGetLastError() == hipSuccess ? DCT_OK : DCT_ERR_DEVICE; }
+
+// Quantizer constants for Q[u][v] = 1 + (1 + u + v) qs, indexed by u + v.
+// magic = ceil(2^k / Q) with k = 14 + ceil(log2 Q): for m < 2^14 the error
+// term m (magic Q - 2^k) / (Q 2^k) stays below 1/Q, so (m magic) >> k is
+// exactly floor(m / Q), and m magic < 2^14 (2^15 + 1) fits in 32 bits.
+dct::QuantArgs quant_args(int qs) {
+  dct::QuantArgs qa{};
+  for (int s = 0; s < 15; ++s) {
+    const int32_t Q = 1 + (1 + s) * qs;
+    int lg = 0;
+    while ((1 << lg) < Q) ++lg;
+    const int k = 14 + lg;
+    qa.Q[s] = Q;
+    qa.half[s] = Q << (dct::kFrac + 2);
+    qa.magic[s] = static_cast<uint32_t>(((uint64_t{1} << k) + Q - 1) / Q);
+    qa.shift[s] = k;
+  }
+  return qa;
+}
+
+unsigned grid_for(int64_t items) { return static_cast<unsigned>((items + dct::kWg - 1) / dct::kWg); }
+
+}  // namespace
+
+extern "C" {
+
+int dct_forward(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t *coef,
+                void *stream) {
+  if (!plane_ok(src, W, H, src_stride) || coef == nullptr || !aligned(coef, 16)) return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  dct::forward_kernel<<<grid_for(nblocks), dct::kWg, 0, as_stream(stream)>>>(src, W, H, src_stride, bw,
+                                                                           nblocks, coef);
+  return launched();
+}
+
+int dct_quantize(const int32_t *coef, int64_t nblocks, int32_t qs, int16_t *qcoef, void *stream) {
+  if (nblocks < 0 || nblocks > (int64_t{1} << 28) || qs < 1 || qs > kMaxQs) return DCT_ERR_INVALID;
+  if (nblocks == 0) return DCT_OK;
+  if (coef == nullptr || qcoef == nullptr || !aligned(coef, 16) || !aligned(qcoef, 16))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int64_t nrows = nblocks * 8;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(nrows), 1 << 20));
+  dct::quantize_kernel<<<grid, dct::kWg, 0, as_stream(stream)>>>(coef, nrows, qs, qcoef);
+  return launched();
+}
+
+int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, uint8_t *dst,
+                int32_t dst_stride, void *stream) {
+  if (!plane_ok(dst, W, H, dst_stride) || qcoef == nullptr || !aligned(qcoef, 16) || qs < 1 ||
+      qs > kMaxQs)
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  dct::inverse_kernel<<<grid_for(nblocks), dct::kWg, 0, as_stream(stream)>>>(qcoef, quant_args(qs), W, H,
+                                                                           bw, nblocks, dst, dst_stride);
+  return launched();
+}
+
+int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W,
+             int32_t H, double peak, double *psnr_host, uint64_t *sse_host, void *stream) {
+  if (!plane_ok(a, W, H, a_stride) || !plane_ok(b, W, H, b_stride) || psnr_host == nullptr ||
+      !(peak >= 0.0) || std::isinf(peak))
+    return DCT_ERR_INVALID;
+  int dev = 0;
+  if (int st = check_device(&dev)) return st;
+  std::lock_guard<std::mutex> guard(g_lock);
+  if (g_scratch[dev] == nullptr) {
+    void *p = nullptr;
+    if (hipMalloc(&p, 2 * sizeof(unsigned long long)) != hipSuccess) return DCT_ERR_NOMEM;
+    g_scratch[dev] = static_cast<unsigned long long *>(p);
+  }
+  unsigned long long *acc = g_scratch[dev];
+  hipStream_t s = as_stream(stream);
+  dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 2);
+  if (launched()) return DCT_ERR_DEVICE;
+  const int64_t items = static_cast<int64_t>((W + 7) / 8) * H;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(items), 4096));
+  dct::sse_kernel<<<grid, dct::kWg, 0, s>>>(a, a_stride, b, b_stride, W, H, acc);
+  if (launched()) return DCT_ERR_DEVICE;
+  unsigned long long host[2] = {0, 0};
+  if (hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return DCT_ERR_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return DCT_ERR_DEVICE;
+  const uint64_t sse = host[0];
+  const double mx = peak > 0.0 ? peak : static_cast<double>(static_cast<uint32_t>(host[1]));
+  if (sse_host) *sse_host = sse;
+  if (sse == 0) {
+    *psnr_host = std::numeric_limits<double>::infinity();
+  } else {
+    const double mse = static_cast<double>(sse) / (static_cast<double>(W) * static_cast<double>(H));
+    *psnr_host = 20.0 * std::log10(mx / std::sqrt(mse));
+  }
+  return DCT_OK;
+}
+
+int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+              int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+  if (!plane_ok(src, W, H, src_stride) || !plane_ok(dst, W, H, dst_stride) || qs < 1 || qs > kMaxQs ||
+      sse_dev == nullptr || !aligned(sse_dev, 8) ||
+      (qcoef_or_null != nullptr && !aligned(qcoef_or_null, 16)))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  hipStream_t s = as_stream(stream);
+  auto *acc = reinterpret_cast<unsigned long long *>(sse_dev);
+  dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 1);
+  if (launched()) return DCT_ERR_DEVICE;
+  const dct::QuantArgs qa = quant_args(qs);
+  if (qcoef_or_null)
+    dct::codec_kernel<true><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
+                                                                  dst_stride, qcoef_or_null, acc);
+  else
+    dct::codec_kernel<false><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa,
+                                                                   dst, dst_stride, nullptr, acc);
+  return launched();
+}
+
+int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits) {
+  if (n_iter == nullptr || frac_bits == nullptr || comp_bits == nullptr) return DCT_ERR_INVALID;
+  *n_iter = dct::kIter;
+  *frac_bits = dct::kFrac;
+  *comp_bits = dct::kComp;
+  return DCT_OK;
+}
+
+int dct_recipe_tables(int32_t *directions, int32_t *gains) {
+  if (directions == nullptr || gains == nullptr) return DCT_ERR_INVALID;
+  for (int r = 0; r < 3; ++r)
+    for (int i = 0; i < dct::kIter; ++i) directions[r * dct::kIter + i] = dct::kTables.dir[r][i];
+  for (int r = 0; r < 3; ++r) gains[r] = dct::kTables.gain[r];
+  gains[3] = dct::kTables.sqrt2;
+  return DCT_OK;
+}
+
+const char *dct_status_string(int status) {
+  switch (status) {
+    case DCT_OK: return "ok";
+    case DCT_ERR_INVALID: return "invalid argument";
+    case DCT_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+    case DCT_ERR_DEVICE: return "HIP runtime error";
+    case DCT_ERR_NOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+int dct_shutdown(void) {
+  std::lock_guard<std::mutex> guard(g_lock);
+  int rc = DCT_OK;
+  for (auto &p : g_scratch) {
+    if (p != nullptr) {
+      if (hipFree(p) != hipSuccess) rc = DCT_ERR_DEVICE;
+      p = nullptr;
+    }
+  }
+  return rc;
+}
+
+}  // extern "C"

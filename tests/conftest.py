@@ -17,11 +17,3 @@ def oracle_mod():
     import oracle
     oracle.lib()
     return oracle
-
-
-def gpu_available() -> bool:
-    try:
-        import torch
-        return torch.cuda.is_available()
-    except Exception:
-        return False

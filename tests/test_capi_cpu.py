@@ -1,0 +1,152 @@
+"""The C-ABI library without a GPU: it loads, exports every declared entry point,
+derives the same recipe constants as the oracle (independently: compile-time
+series in the library, libm in the oracle), and rejects invalid arguments
+before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1306_1373_amd import build as hbuild
+from paper_1306_1373_amd import codec
+
+HEADER = os.path.join(hbuild.INCLUDE, "dctcodec.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hbuild.LIB):
+        hbuild.build()
+    return codec.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"DCT_API\s+(?:const\s+)?\w+\s*\*?\s*(dct_\w+)\s*\(", text)
+
+
+def test_header_declares_the_boundary():
+    names = set(declared_functions())
+    assert {"dct_forward", "dct_quantize", "dct_inverse", "dct_psnr", "dct_codec",
+            "dct_recipe_info", "dct_recipe_tables", "dct_status_string", "dct_shutdown"} <= names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    for name in declared_functions():
+        assert name in codec._PROTOS, f"binding lacks a prototype for {name}"
+
+
+def test_recipe_constants_agree_with_oracle(lib, oracle_mod):
+    assert codec.recipe_info() == oracle_mod.recipe_info()
+    dirs, gains = codec.recipe_tables()
+    odirs, ogains = oracle_mod.recipe_tables()
+    assert np.array_equal(np.array(dirs), odirs)
+    assert list(gains) == [int(g) for g in ogains]
+
+
+def test_status_strings(lib):
+    assert codec.status_string(0) == "ok"
+    assert "invalid" in codec.status_string(-1)
+    assert codec.status_string(-99) == "unknown status"
+
+
+P8 = C.c_void_p(4096)     # aligned non-null placeholders: validation never dereferences
+P16 = C.c_void_p(8192)
+MIS = C.c_void_p(4100)    # 4-byte aligned only
+
+
+@pytest.mark.parametrize("args", [
+    (None, 8, 8, 8, P16),           # null source
+    (P8, 0, 8, 8, P16),             # W = 0
+    (P8, 8, 0, 8, P16),             # H = 0
+    (P8, 65536, 8, 65536, P16),     # W too large
+    (P8, 9, 8, 12, P16),            # stride not a multiple of 8
+    (P8, 16, 8, 8, P16),            # stride < W
+    (MIS, 8, 8, 8, P16),            # misaligned source
+    (P8, 8, 8, 8, None),            # null coefficients
+    (P8, 8, 8, 8, C.c_void_p(4104)),  # misaligned coefficients
+])
+def test_forward_rejects(lib, args):
+    assert lib.dct_forward(*args, None) == codec.DCT_ERR_INVALID
+
+
+def test_quantize_rejects(lib):
+    assert lib.dct_quantize(P16, -1, 4, P16, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_quantize(P16, 4, 0, P16, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_quantize(P16, 4, 1025, P16, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_quantize(None, 4, 4, P16, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_quantize(P16, 4, 4, C.c_void_p(8200), None) == codec.DCT_ERR_INVALID
+    assert lib.dct_quantize(None, 0, 4, None, None) == codec.DCT_OK  # nothing to do
+
+
+def test_inverse_rejects(lib):
+    assert lib.dct_inverse(None, 4, 8, 8, P8, 8, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_inverse(P16, 0, 8, 8, P8, 8, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_inverse(P16, 4, 8, 8, None, 8, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_inverse(P16, 4, 8, 8, P8, 4, None) == codec.DCT_ERR_INVALID
+
+
+def test_psnr_rejects(lib):
+    out = C.c_double()
+    assert lib.dct_psnr(P8, 8, P8, 8, 8, 8, -1.0, C.byref(out), None, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_psnr(P8, 8, P8, 8, 8, 8, float("inf"), C.byref(out), None, None) == \
+        codec.DCT_ERR_INVALID
+    assert lib.dct_psnr(P8, 8, P8, 8, 8, 8, float("nan"), C.byref(out), None, None) == \
+        codec.DCT_ERR_INVALID
+    assert lib.dct_psnr(P8, 8, P8, 8, 8, 8, 255.0, None, None, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_psnr(P8, 8, None, 8, 8, 8, 255.0, C.byref(out), None, None) == \
+        codec.DCT_ERR_INVALID
+
+
+def test_codec_rejects(lib):
+    ok = (P8, 8, 8, 8, 4, P8, 8, None, P8, None)
+    bad = [
+        (None,) + ok[1:],
+        ok[:4] + (0,) + ok[5:],
+        ok[:4] + (2000,) + ok[5:],
+        ok[:5] + (None,) + ok[6:],
+        ok[:6] + (12,) + ok[7:],
+        ok[:7] + (C.c_void_p(4104),) + ok[8:],
+        ok[:8] + (None, None),
+        ok[:8] + (C.c_void_p(4100), None),
+    ]
+    for args in bad:
+        assert lib.dct_codec(*args) == codec.DCT_ERR_INVALID, args
+
+
+def test_recipe_info_rejects_null(lib):
+    n = C.c_int32()
+    assert lib.dct_recipe_info(C.byref(n), None, C.byref(n)) == codec.DCT_ERR_INVALID
+    assert lib.dct_recipe_tables(None, None) == codec.DCT_ERR_INVALID
+
+
+def test_quantizer_magic_lemma():
+    # The fused kernel divides m < 2^14 by Q as (m * ceil(2^k / Q)) >> k with
+    # k = 14 + ceil(log2 Q), using 24-bit multiplies.  Check that lemma for every
+    # table entry of every qs the library accepts (exhaustively over m).
+    m = np.arange(1 << 14, dtype=np.int64)
+    Qs = sorted({1 + (1 + s) * qs for qs in range(1, 1025) for s in range(15)})
+    for Q in Qs:
+        k = 14 + (Q - 1).bit_length()       # 2^(k-14) is the smallest power of two >= Q
+        magic = -(-(1 << k) // Q)
+        assert magic < (1 << 24)
+        prod = m * magic
+        assert prod.max() < (1 << 32)
+        assert np.array_equal(prod >> k, m // Q), Q
+
+
+def test_bands_match_whole_image(oracle_mod):
+    # the band-parallel oracle harness gives the whole-image results
+    from oracle import bands
+    from paper_1306_1373_amd.synth import synth_image
+    img = synth_image(203, 141, 2, 5.0)
+    rec, s, q = oracle_mod.cordic_codec(img, 4, want_q=True)
+    rec2, s2, q2 = bands.codec_bands(img, 4, threads=3, want_q=True)
+    assert s == s2 and np.array_equal(rec, rec2) and np.array_equal(q, q2)
+    assert np.array_equal(bands.forward_bands(img, threads=3), oracle_mod.cordic_forward(img))
+    assert np.array_equal(bands.inverse_bands(q, 4, 203, 141, threads=3),
+                          oracle_mod.cordic_inverse(q, 4, 203, 141))
