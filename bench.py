@@ -23,10 +23,13 @@ W = H = 8192
 QS = 4
 N_IMAGES = 5
 
-# MI355X published figures
+# MI355X published figures.  VALU issue: 256 CUs x 4 SIMDs x 32 lanes per clock for
+# 32-bit add / subtract / shift / logic (the rate behind the 157.3 TFLOP/s FP32
+# vector figure, an FMA counting 2) at 2.4 GHz; multiplies, funnel shifts and
+# 64-bit multiply-adds issue at half that rate.
 HBM_PEAK_GBPS = 8000.0
-CU, LANES_PER_CLK, CLOCK_GHZ = 256, 64, 2.4       # 4 SIMD x 16 lanes per CU per clock
-INT32_PEAK_TOPS = CU * LANES_PER_CLK * CLOCK_GHZ / 1000.0   # 39.3 Tops/s (non-packed int32 VALU)
+CU, LANES_PER_CLK, CLOCK_GHZ = 256, 128, 2.4
+INT32_PEAK_TOPS = CU * LANES_PER_CLK * CLOCK_GHZ / 1000.0   # 78.6 Tops/s
 
 # Algorithmic integer operations of recipe R(10, 12, 15) per 8x8 block, counting
 # every add, subtract, shift, multiply, compare/select and division once:
@@ -47,7 +50,21 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity check")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain 64 MiB device-to-device copies (the reference kernel "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    n = 64 << 20
+    a = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": n, "dispatches": 5}), flush=True)
 
 
 def cpu_baseline(img, qs):
@@ -69,6 +86,9 @@ def main():
               "(the codec's blocks are independent: each GPU would run this same kernel on "
               "its own band of block rows)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import numpy as np
     import torch
 

@@ -43,19 +43,24 @@ struct QuantArgs {
 // Packed source pixels of the lane's block: word 2r holds pixels 0..3 of row r,
 // word 2r+1 pixels 4..7 (little-endian bytes).  Rows past H repeat row H-1 and
 // columns past W repeat column W-1; no byte outside the W x H region is read.
+// The full-width case (every block but the last of a block row when W is not a
+// multiple of 8) is one branch around eight independent 8-byte loads, so they
+// are all in flight together.
 __device__ __forceinline__ void load_block(const uint8_t *__restrict__ src, int W, int H, int stride,
                                            int by, int bx, uint32_t (&pix)[16]) {
   const int x0 = bx * 8;
-  const bool full = x0 + 8 <= W;
+  if (x0 + 8 <= W) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int y = min(by * 8 + r, H - 1);
-    const uint8_t *row = src + static_cast<size_t>(y) * stride;
-    if (full) {
-      const uint2 w = *reinterpret_cast<const uint2 *>(row + x0);
+    for (int r = 0; r < 8; ++r) {
+      const int y = min(by * 8 + r, H - 1);
+      const uint2 w = *reinterpret_cast<const uint2 *>(src + static_cast<size_t>(y) * stride + x0);
       pix[2 * r] = w.x;
       pix[2 * r + 1] = w.y;
-    } else {
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint8_t *row = src + static_cast<size_t>(min(by * 8 + r, H - 1)) * stride;
       uint32_t lo = 0, hi = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -140,19 +145,21 @@ __device__ __forceinline__ void pack_block(const int (&x)[64], uint32_t (&rec)[1
   }
 }
 
-// Store the W x H part of a packed block.
+// Store the W x H part of a packed block (one branch for the full-width case).
 __device__ __forceinline__ void store_block(uint8_t *__restrict__ dst, int W, int H, int stride,
                                             int by, int bx, const uint32_t (&rec)[16]) {
   const int x0 = bx * 8;
-  const bool full = x0 + 8 <= W;
+  if (x0 + 8 <= W && by * 8 + 8 <= H) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int y = by * 8 + r;
-    if (y < H) {
-      uint8_t *row = dst + static_cast<size_t>(y) * stride;
-      if (full) {
-        *reinterpret_cast<uint2 *>(row + x0) = make_uint2(rec[2 * r], rec[2 * r + 1]);
-      } else {
+    for (int r = 0; r < 8; ++r)
+      *reinterpret_cast<uint2 *>(dst + static_cast<size_t>(by * 8 + r) * stride + x0) =
+          make_uint2(rec[2 * r], rec[2 * r + 1]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int y = by * 8 + r;
+      if (y < H) {
+        uint8_t *row = dst + static_cast<size_t>(y) * stride;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (x0 + j < W) row[x0 + j] = static_cast<uint8_t>(rec[2 * r + (j >> 2)] >> (8 * (j & 3)));
