@@ -28,7 +28,8 @@
  *
  * Conventions shared by every entry point:
  *   - Planes are uint8 grayscale, row-major, W x H pixels, rows `stride` bytes
- *     apart.  stride >= W and stride % 8 == 0; the plane pointer is 8-byte
+ *     apart.  stride >= W, stride % 8 == 0 and (H - 1) * stride + W < 2^32 (the
+ *     kernels address a plane with 32-bit offsets); the plane pointer is 8-byte
  *     aligned.  A source plane must hold (H - 1) * stride + W readable bytes; the
  *     library reads no byte outside the W x H region.  A destination plane gets
  *     exactly its W x H region written; pad bytes are left untouched.

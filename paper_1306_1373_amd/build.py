@@ -32,6 +32,18 @@ FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 over the device and host sources of the library: profiles record
+    it so that counter figures are only reused for the kernels they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(SOURCES + HEADERS):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, extra=None, out: str = LIB) -> str:
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp"

@@ -25,9 +25,12 @@ std::array<int, kMaxDevices> g_arch_ok{};            // 0 unknown, 1 gfx950, -1 
 
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
+// The kernels address a plane with 32-bit offsets: (H - 1) stride + W < 2^32.
 bool plane_ok(const void *p, int32_t W, int32_t H, int32_t stride) {
   return p != nullptr && aligned(p, 8) && W >= 1 && W <= kMaxDim && H >= 1 && H <= kMaxDim &&
-         stride >= W && stride % 8 == 0;
+         stride >= W && stride % 8 == 0 &&
+         static_cast<uint64_t>(H - 1) * static_cast<uint64_t>(stride) + static_cast<uint64_t>(W) <
+             (uint64_t{1} << 32);
 }
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
@@ -51,26 +54,31 @@ int check_device(int *dev_out) {
 
 int launched() { return hipGetLastError() == hipSuccess ? DCT_OK : DCT_ERR_DEVICE; }
 
-// Quantizer constants for Q[u][v] = 1 + (1 + u + v) qs, indexed by u + v.
-// magic = ceil(2^k / Q) with k = 14 + ceil(log2 Q): for m < 2^14 the error
-// term m (magic Q - 2^k) / (Q 2^k) stays below 1/Q, so (m magic) >> k is
-// exactly floor(m / Q), and m magic < 2^14 (2^15 + 1) fits in 32 bits.
-dct::QuantArgs quant_args(int qs) {
-  dct::QuantArgs qa{};
+// Quantizer of the fused codec for Q[u][v] = 1 + (1 + u + v) qs, indexed by u + v:
+// the smallest float r >= 1/Q makes trunc(float(m) r) = floor(m / Q) for every
+// m < 2^14 (the lemma the CPU tests check for every table entry).
+dct::CodecQuant codec_quant(int qs) {
+  dct::CodecQuant qa{};
   for (int s = 0; s < 15; ++s) {
     const int32_t Q = 1 + (1 + s) * qs;
-    int lg = 0;
-    while ((1 << lg) < Q) ++lg;
-    const int k = 14 + lg;
-    qa.Q[s] = Q;
+    float r = static_cast<float>(1.0 / Q);
+    if (static_cast<double>(r) < 1.0 / Q) r = std::nextafter(r, std::numeric_limits<float>::infinity());
+    qa.rcp[s] = r;
+    qa.qscale[s] = static_cast<float>(Q) * static_cast<float>(1 << dct::kFrac);
     qa.half[s] = Q << (dct::kFrac + 2);
-    qa.magic[s] = static_cast<uint32_t>(((uint64_t{1} << k) + Q - 1) / Q);
-    qa.shift[s] = k;
   }
   return qa;
 }
 
-unsigned grid_for(int64_t items) { return static_cast<unsigned>((items + dct::kWg - 1) / dct::kWg); }
+dct::DequantTable dequant_table(int qs) {
+  dct::DequantTable dq{};
+  for (int s = 0; s < 15; ++s) dq.Q[s] = 1 + (1 + s) * qs;
+  return dq;
+}
+
+unsigned grid_for(int64_t items, int threads = dct::kWg) {
+  return static_cast<unsigned>((items + threads - 1) / threads);
+}
 
 }  // namespace
 
@@ -81,8 +89,8 @@ int dct_forward(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, in
   if (!plane_ok(src, W, H, src_stride) || coef == nullptr || !aligned(coef, 16)) return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
   const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
-  dct::forward_kernel<<<grid_for(nblocks), dct::kWg, 0, as_stream(stream)>>>(src, W, H, src_stride, bw,
-                                                                           nblocks, coef);
+  dct::forward_kernel<<<grid_for(nblocks, dct::kBlockThreads), dct::kBlockThreads, 0, as_stream(stream)>>>(
+      src, W, H, src_stride, bw, nblocks, coef);
   return launched();
 }
 
@@ -105,8 +113,8 @@ int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, uint8_t 
     return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
   const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
-  dct::inverse_kernel<<<grid_for(nblocks), dct::kWg, 0, as_stream(stream)>>>(qcoef, quant_args(qs), W, H,
-                                                                           bw, nblocks, dst, dst_stride);
+  dct::inverse_kernel<<<grid_for(nblocks, dct::kBlockThreads), dct::kBlockThreads, 0, as_stream(stream)>>>(
+      qcoef, dequant_table(qs), W, H, bw, nblocks, dst, dst_stride);
   return launched();
 }
 
@@ -158,13 +166,14 @@ int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int3
   auto *acc = reinterpret_cast<unsigned long long *>(sse_dev);
   dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 1);
   if (launched()) return DCT_ERR_DEVICE;
-  const dct::QuantArgs qa = quant_args(qs);
+  const dct::CodecQuant qa = codec_quant(qs);
+  const unsigned grid = grid_for(nblocks, dct::kBlockThreads);
   if (qcoef_or_null)
-    dct::codec_kernel<true><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
-                                                                  dst_stride, qcoef_or_null, acc);
+    dct::codec_kernel<true><<<grid, dct::kBlockThreads, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
+                                                               dst_stride, qcoef_or_null, acc);
   else
-    dct::codec_kernel<false><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa,
-                                                                   dst, dst_stride, nullptr, acc);
+    dct::codec_kernel<false><<<grid, dct::kBlockThreads, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
+                                                                dst_stride, nullptr, acc);
   return launched();
 }
 

@@ -1,20 +1,29 @@
-// transform.hpp -- device-side 8-point Cordic-based Loeffler flow graphs.
+// transform.hpp -- device-side Cordic-based Loeffler flow graphs on register blocks.
 //
-// One call transforms eight int32 values held in registers.  The forward graph
-// is the four-stage Loeffler 8-point DCT of Sec. 2.5.2 (stage 1 butterflies;
-// stage 2 even butterflies and the odd 3pi/16 and pi/16 rotations; stage 3 the
-// DC/Nyquist butterfly, the sqrt(2)-scaled 6pi/16 rotation and the odd
-// butterflies; stage 4 the last odd butterfly and two sqrt(2) factors).  Its
-// output is 2 sqrt(2) times the orthonormal DCT-II of the input, in the same
-// fixed point.  The inverse graph is its transpose: stages in reverse order,
-// every rotation by -theta.
+// The forward graph is the four-stage Loeffler 8-point DCT of Sec. 2.5.2:
+//   stage 1  butterflies s_i = x_i + x_{7-i}, d_i = x_i - x_{7-i};
+//   stage 2  even half: e0 = s0 + s3, e3 = s0 - s3, e1 = s1 + s2, e2 = s1 - s2;
+//            odd half: (u4, u7) = R(d3, d0; 3pi/16), (u5, u6) = R(d2, d1; pi/16);
+//   stage 3  Z0 = e0 + e1, Z4 = e0 - e1, (Z2, Z6) = sqrt2 R(e2, e3; 6pi/16);
+//            v4 = u4 + u6, v6 = u4 - u6, v7 = u7 + u5, v5 = u7 - u5;
+//   stage 4  Z1 = v7 + v4, Z7 = v7 - v4, Z3 = sqrt2 v5, Z5 = sqrt2 v6,
+// with R(a, b; t) = (a cos t + b sin t, -a sin t + b cos t).  Its output is
+// 2 sqrt(2) times the orthonormal DCT-II of its input, in the same fixed point.
+// The inverse graph is the transpose: the stages in reverse order with every
+// rotation by -t.
 //
-// Every rotation block is kIter micro-rotations with the directions of
-// recipe.hpp resolved at compile time (so each step is two shifts and two
-// adds), followed by the gain compensation (v M + 2^(P-1)) >> P with a 64-bit
-// product.  All shifts are arithmetic; the values never leave int32 (the
-// largest magnitude any step stores is below 2^29 for every input a uint8 plane
-// or a clamped dequantized block can produce).
+// Every rotation block is kIter micro-rotations a' = a + d_i (b >> i),
+// b' = b - d_i (a >> i), directions resolved at compile time, followed by the
+// gain compensation (v M + 2^(P-1)) >> P of each output.  All shifts are
+// arithmetic; no value leaves int32 (the largest magnitude any step stores is
+// below 2^29 for every input a uint8 plane or a clamped dequantized block gives).
+//
+// A pass transforms all eight lines (rows or columns) of a register block at
+// once and keeps the instruction kinds apart: the butterflies and micro-
+// rotations of all lines are plain 32-bit adds, subtracts and shifts, which
+// gfx950 can issue two at a time across waves, while the 64-bit multiply-adds
+// of the gain compensations, which it cannot, are gathered into runs.  A
+// scheduling barrier between the regions keeps the compiler from mixing them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,114 +32,161 @@
 
 namespace dct {
 
-// kIter micro-rotations, step I onwards; S = +1 rotates by +theta, S = -1 by -theta
-template <int R, int S, int I = 0>
-__device__ __forceinline__ void cordic_steps(int &a, int &b) {
-  if constexpr (I < kIter) {
-    constexpr int d = S * kTables.dir[R][I];
-    const int sa = a >> I;
-    const int sb = b >> I;
-    if constexpr (d > 0) {
-      a = a + sb;
-      b = b - sa;
-    } else {
-      a = a - sb;
-      b = b + sa;
-    }
-    cordic_steps<R, S, I + 1>(a, b);
+// keep the compiler from moving instructions across this point
+__device__ __forceinline__ void region() { __builtin_amdgcn_sched_barrier(0); }
+
+// one micro-rotation step I of rotation block R; S = +1 rotates by +theta, -1 by -theta
+template <int R, int S, int I>
+__device__ __forceinline__ void cordic_step(int &a, int &b) {
+  constexpr int d = S * kTables.dir[R][I];
+  const int sa = a >> I;
+  const int sb = b >> I;
+  if constexpr (d > 0) {
+    a = a + sb;
+    b = b - sa;
+  } else {
+    a = a - sb;
+    b = b + sa;
   }
 }
 
-// multiply by M / 2^P, rounding half up
+// multiply by M / 2^P, rounding half up: (v M + 2^(P-1)) >> P with a 64-bit product
 template <int32_t M>
 __device__ __forceinline__ int compensate(int v) {
   return static_cast<int>((static_cast<long long>(v) * M + (1LL << (kComp - 1))) >> kComp);
 }
 
-// rotation block R(a, b; S theta_R) = (a cos + b sin, -a sin + b cos), scaled
-// by sqrt(2) for the 6pi/16 block
-template <int R, int S>
-__device__ __forceinline__ void rotate(int &a, int &b) {
-  cordic_steps<R, S>(a, b);
-  a = compensate<kTables.gain[R]>(a);
-  b = compensate<kTables.gain[R]>(b);
+// the micro-rotations of the three rotation blocks of all eight lines, step by step
+template <int S, int I = 0>
+__device__ __forceinline__ void cordic_lines(int (&a1)[8], int (&b1)[8], int (&a3)[8], int (&b3)[8],
+                                             int (&a6)[8], int (&b6)[8]) {
+  if constexpr (I < kIter) {
+#pragma unroll
+    for (int L = 0; L < 8; ++L) {
+      cordic_step<kRot1, S, I>(a1[L], b1[L]);
+      cordic_step<kRot3, S, I>(a3[L], b3[L]);
+      cordic_step<kRot6, S, I>(a6[L], b6[L]);
+    }
+    cordic_lines<S, I + 1>(a1, b1, a3, b3, a6, b6);
+  }
 }
 
-// forward 8-point graph, in place: x0..x7 -> Z0..Z7
-__device__ __forceinline__ void loeffler_fwd(int &x0, int &x1, int &x2, int &x3, int &x4, int &x5,
-                                             int &x6, int &x7) {
-  // stage 1
-  const int s0 = x0 + x7, s1 = x1 + x6, s2 = x2 + x5, s3 = x3 + x4;
-  const int d0 = x0 - x7, d1 = x1 - x6, d2 = x2 - x5, d3 = x3 - x4;
-  // stage 2
-  const int e0 = s0 + s3, e3 = s0 - s3, e1 = s1 + s2, e2 = s1 - s2;
-  int u4 = d3, u7 = d0, u5 = d2, u6 = d1;
-  rotate<kRot3, +1>(u4, u7);
-  rotate<kRot1, +1>(u5, u6);
-  // stage 3
-  int z2 = e2, z6 = e3;
-  rotate<kRot6, +1>(z2, z6);
-  const int v4 = u4 + u6, v6 = u4 - u6, v7 = u7 + u5, v5 = u7 - u5;
-  // stage 4
-  x0 = e0 + e1;
-  x4 = e0 - e1;
-  x2 = z2;
-  x6 = z6;
-  x1 = v7 + v4;
-  x7 = v7 - v4;
-  x3 = compensate<kTables.sqrt2>(v5);
-  x5 = compensate<kTables.sqrt2>(v6);
+// the gain compensations of the three rotation blocks of all eight lines
+__device__ __forceinline__ void gains_lines(int (&a1)[8], int (&b1)[8], int (&a3)[8], int (&b3)[8],
+                                            int (&a6)[8], int (&b6)[8]) {
+#pragma unroll
+  for (int L = 0; L < 8; ++L) {
+    a1[L] = compensate<kTables.gain[kRot1]>(a1[L]);
+    b1[L] = compensate<kTables.gain[kRot1]>(b1[L]);
+    a3[L] = compensate<kTables.gain[kRot3]>(a3[L]);
+    b3[L] = compensate<kTables.gain[kRot3]>(b3[L]);
+    a6[L] = compensate<kTables.gain[kRot6]>(a6[L]);
+    b6[L] = compensate<kTables.gain[kRot6]>(b6[L]);
+  }
 }
 
-// inverse (transposed) 8-point graph, in place: Z0..Z7 -> x0..x7
-__device__ __forceinline__ void loeffler_inv(int &z0, int &z1, int &z2, int &z3, int &z4, int &z5,
-                                             int &z6, int &z7) {
-  // stage 4 transposed
-  const int v7 = z1 + z7, v4 = z1 - z7;
-  const int v5 = compensate<kTables.sqrt2>(z3), v6 = compensate<kTables.sqrt2>(z5);
-  // stage 3 transposed
-  const int e0 = z0 + z4, e1 = z0 - z4;
-  int e2 = z2, e3 = z6;
-  rotate<kRot6, -1>(e2, e3);
-  int u4 = v4 + v6, u6 = v4 - v6, u7 = v7 + v5, u5 = v7 - v5;
-  // stage 2 transposed
-  rotate<kRot3, -1>(u4, u7);
-  rotate<kRot1, -1>(u5, u6);
-  const int s0 = e0 + e3, s3 = e0 - e3, s1 = e1 + e2, s2 = e1 - e2;
-  // stage 1 transposed (d0 = u7, d1 = u6, d2 = u5, d3 = u4)
-  z0 = s0 + u7;
-  z7 = s0 - u7;
-  z1 = s1 + u6;
-  z6 = s1 - u6;
-  z2 = s2 + u5;
-  z5 = s2 - u5;
-  z3 = s3 + u4;
-  z4 = s3 - u4;
+// element k of line L: rows when kRows, columns otherwise
+template <bool kRows>
+__device__ __forceinline__ int &at(int (&x)[64], int line, int k) {
+  return kRows ? x[line * 8 + k] : x[k * 8 + line];
 }
 
-// 2-D forward on a register block x[i*8 + j]: row pass, then column pass.
-// Input (p - 128) << F; output c[u*8 + v] with coefficient = c / 2^(F+3).
-__device__ __forceinline__ void forward_block(int (&x)[64]) {
+// forward graph on the eight rows (kRows) or columns of a block, in place
+template <bool kRows>
+__device__ __forceinline__ void forward_pass(int (&x)[64]) {
+  int e0[8], e1[8], a6[8], b6[8], a3[8], b3[8], a1[8], b1[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-    loeffler_fwd(x[i * 8 + 0], x[i * 8 + 1], x[i * 8 + 2], x[i * 8 + 3], x[i * 8 + 4], x[i * 8 + 5],
-                 x[i * 8 + 6], x[i * 8 + 7]);
+  for (int L = 0; L < 8; ++L) {
+    int v[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
-    loeffler_fwd(x[0 * 8 + j], x[1 * 8 + j], x[2 * 8 + j], x[3 * 8 + j], x[4 * 8 + j], x[5 * 8 + j],
-                 x[6 * 8 + j], x[7 * 8 + j]);
+    for (int k = 0; k < 8; ++k) v[k] = at<kRows>(x, L, k);
+    // stage 1
+    const int s0 = v[0] + v[7], s1 = v[1] + v[6], s2 = v[2] + v[5], s3 = v[3] + v[4];
+    const int d0 = v[0] - v[7], d1 = v[1] - v[6], d2 = v[2] - v[5], d3 = v[3] - v[4];
+    // stage 2, even half; the rotation inputs
+    e0[L] = s0 + s3;
+    e1[L] = s1 + s2;
+    a6[L] = s1 - s2;  // e2
+    b6[L] = s0 - s3;  // e3
+    a3[L] = d3;       // (u4, u7) = R(d3, d0; 3pi/16)
+    b3[L] = d0;
+    a1[L] = d2;       // (u5, u6) = R(d2, d1; pi/16)
+    b1[L] = d1;
+  }
+  cordic_lines<+1>(a1, b1, a3, b3, a6, b6);
+  region();
+  gains_lines(a1, b1, a3, b3, a6, b6);
+  region();
+  int v5[8], v6[8];
+#pragma unroll
+  for (int L = 0; L < 8; ++L) {
+    // stage 3
+    const int v4 = a3[L] + b1[L], v7 = b3[L] + a1[L];
+    v6[L] = a3[L] - b1[L];
+    v5[L] = b3[L] - a1[L];
+    at<kRows>(x, L, 0) = e0[L] + e1[L];
+    at<kRows>(x, L, 4) = e0[L] - e1[L];
+    at<kRows>(x, L, 2) = a6[L];
+    at<kRows>(x, L, 6) = b6[L];
+    // stage 4, butterfly
+    at<kRows>(x, L, 1) = v7 + v4;
+    at<kRows>(x, L, 7) = v7 - v4;
+  }
+  region();
+  // stage 4, the two sqrt(2) factors
+#pragma unroll
+  for (int L = 0; L < 8; ++L) {
+    at<kRows>(x, L, 3) = compensate<kTables.sqrt2>(v5[L]);
+    at<kRows>(x, L, 5) = compensate<kTables.sqrt2>(v6[L]);
+  }
+  region();
 }
 
-// 2-D inverse on a register block: column pass, then row pass.
-__device__ __forceinline__ void inverse_block(int (&x)[64]) {
+// inverse (transposed) graph on the eight columns or rows of a block, in place
+template <bool kRows>
+__device__ __forceinline__ void inverse_pass(int (&x)[64]) {
+  // stage 4 transposed: v5 = sqrt2 Z3, v6 = sqrt2 Z5
+  int v5[8], v6[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
-    loeffler_inv(x[0 * 8 + j], x[1 * 8 + j], x[2 * 8 + j], x[3 * 8 + j], x[4 * 8 + j], x[5 * 8 + j],
-                 x[6 * 8 + j], x[7 * 8 + j]);
+  for (int L = 0; L < 8; ++L) {
+    v5[L] = compensate<kTables.sqrt2>(at<kRows>(x, L, 3));
+    v6[L] = compensate<kTables.sqrt2>(at<kRows>(x, L, 5));
+  }
+  region();
+  int e0[8], e1[8], a6[8], b6[8], a3[8], b3[8], a1[8], b1[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-    loeffler_inv(x[i * 8 + 0], x[i * 8 + 1], x[i * 8 + 2], x[i * 8 + 3], x[i * 8 + 4], x[i * 8 + 5],
-                 x[i * 8 + 6], x[i * 8 + 7]);
+  for (int L = 0; L < 8; ++L) {
+    const int z0 = at<kRows>(x, L, 0), z1 = at<kRows>(x, L, 1), z2 = at<kRows>(x, L, 2);
+    const int z4 = at<kRows>(x, L, 4), z6 = at<kRows>(x, L, 6), z7 = at<kRows>(x, L, 7);
+    const int v7 = z1 + z7, v4 = z1 - z7;
+    // stage 3 transposed
+    e0[L] = z0 + z4;
+    e1[L] = z0 - z4;
+    a6[L] = z2;  // (e2, e3) = sqrt2 R(Z2, Z6; -6pi/16)
+    b6[L] = z6;
+    a3[L] = v4 + v6[L];  // u4
+    b3[L] = v7 + v5[L];  // u7: (t4, t7) = R(u4, u7; -3pi/16)
+    a1[L] = v7 - v5[L];  // u5
+    b1[L] = v4 - v6[L];  // u6: (t5, t6) = R(u5, u6; -pi/16)
+  }
+  cordic_lines<-1>(a1, b1, a3, b3, a6, b6);
+  region();
+  gains_lines(a1, b1, a3, b3, a6, b6);
+  region();
+#pragma unroll
+  for (int L = 0; L < 8; ++L) {
+    // stage 2 and stage 1 transposed: d0 = t7, d1 = t6, d2 = t5, d3 = t4
+    const int s0 = e0[L] + b6[L], s3 = e0[L] - b6[L], s1 = e1[L] + a6[L], s2 = e1[L] - a6[L];
+    at<kRows>(x, L, 0) = s0 + b3[L];
+    at<kRows>(x, L, 7) = s0 - b3[L];
+    at<kRows>(x, L, 1) = s1 + b1[L];
+    at<kRows>(x, L, 6) = s1 - b1[L];
+    at<kRows>(x, L, 2) = s2 + a1[L];
+    at<kRows>(x, L, 5) = s2 - a1[L];
+    at<kRows>(x, L, 3) = s3 + a3[L];
+    at<kRows>(x, L, 4) = s3 - a3[L];
+  }
+  region();
 }
 
 }  // namespace dct
