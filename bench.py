@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 64 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="no GPU work: condense the rocprofv3 outputs under DIR (subfolders trace, "
+                         "fetch, write, copy_fetch, copy_write, sq) into the JSON given by --out")
+    ap.add_argument("--kernel", default="void dct::codec_kernel<false>",
+                    help="kernel-name prefix for --summarize-profile")
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "codec_kernel_8192.json"))
     return ap.parse_args()
 
 
@@ -65,6 +71,67 @@ def calibrate_copy():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_per_dispatch": n, "dispatches": 5}), flush=True)
+
+
+PROFILE = os.path.join(ROOT, "profiles", "codec_kernel_8192.json")
+COPY_BYTES = 64 << 20
+
+
+def _counter_means(d, prefix):
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[0]
+    vals = {}
+    for r in csv.DictReader(open(f)):
+        if r["Kernel_Name"].startswith(prefix):
+            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}
+
+
+def summarize_profile(root, prefix, out):
+    """Kernel time from the kernel trace, HBM bytes from FETCH_SIZE / WRITE_SIZE scaled
+    by what the same counters read for a plain copy of COPY_BYTES, and the SQ counters."""
+    import csv
+    import glob
+
+    from paper_1306_1373_amd.build import source_digest
+    stats = sorted(glob.glob(os.path.join(root, "trace", "**", "*kernel_stats.csv"), recursive=True))[0]
+    row = [r for r in csv.DictReader(open(stats)) if r["Name"].startswith(prefix)][0]
+    fetch = _counter_means(os.path.join(root, "fetch"), prefix)["FETCH_SIZE"]
+    write = _counter_means(os.path.join(root, "write"), prefix)["WRITE_SIZE"]
+    copy_prefix = "__amd_rocclr_copyBuffer"
+    cfetch = _counter_means(os.path.join(root, "copy_fetch"), copy_prefix)["FETCH_SIZE"]
+    cwrite = _counter_means(os.path.join(root, "copy_write"), copy_prefix)["WRITE_SIZE"]
+    fscale, wscale = COPY_BYTES / 1024 / cfetch, COPY_BYTES / 1024 / cwrite
+    summary = {
+        "kernel": row["Name"].split("(")[0],
+        "source_sha256": source_digest(),
+        "kernel_trace": {"calls": int(row["Calls"]), "avg_ns": float(row["AverageNs"]),
+                         "min_ns": float(row["MinNs"]), "max_ns": float(row["MaxNs"])},
+        "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+        "copy_reference": {"bytes": COPY_BYTES, "fetch_kib": cfetch, "write_kib": cwrite},
+        "fetch_scale": fscale, "write_scale": wscale,
+        "traffic_bytes_per_dispatch": (fetch * fscale + write * wscale) * 1024,
+        "algorithmic_bytes_per_dispatch": BYTES_PER_PIXEL * W * H,
+        "sq": _counter_means(os.path.join(root, "sq"), prefix),
+    }
+    with open(out, "w") as f:
+        json.dump(summary, f, indent=1)
+    print(json.dumps(summary, indent=1))
+
+
+def profiled_traffic():
+    """HBM bytes per codec launch from the committed counter summary, or None when the
+    kernel sources have changed since the counters were taken."""
+    try:
+        from paper_1306_1373_amd.build import source_digest
+        with open(PROFILE) as f:
+            prof = json.load(f)
+        if prof.get("source_sha256") == source_digest():
+            return round(prof["traffic_bytes_per_dispatch"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def cpu_baseline(img, qs):
@@ -88,6 +155,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.kernel, args.out)
         return
     import numpy as np
     import torch
@@ -162,7 +232,7 @@ def main():
                 "bytes_per_pixel": BYTES_PER_PIXEL},
         "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
                      "peak": round(INT32_PEAK_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": None,
+                     "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": profiled_traffic(),
                      "kernel": "codec_kernel<false>", "ops_per_pixel": OPS_PER_PIXEL,
                      "avg_kernel_ms": round(ms_per_step, 5)},
         "deterministic": deterministic,

@@ -117,6 +117,41 @@ DCT_API int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32
 DCT_API int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
               int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
 
+/* Floating-point forms of the transform (the exact DCT of Sec. 2.5.1, eq. (6),
+ * that Sec. 4.1 compares the Cordic-based codec against), for dct_forward_float
+ * and dct_codec_float:
+ *   DCT_FORM_F32_LOEFFLER  the four-stage Loeffler graph in FP32, exact rotations;
+ *   DCT_FORM_MFMA_F16      vec(F) = (C (x) C) vec(p - 128) as a GEMM over blocks on
+ *                          the matrix cores, FP16 inputs (C (x) C rounded once to
+ *                          FP16), FP32 accumulation;
+ *   DCT_FORM_MFMA_BF16     the same with BF16 inputs. */
+typedef enum { DCT_FORM_F32_LOEFFLER = 1, DCT_FORM_MFMA_F16 = 2, DCT_FORM_MFMA_BF16 = 3 } dct_form;
+
+/* Orthonormal 2-D DCT-II coefficients of every 8x8 block in a floating-point form.
+ *   src   W x H uint8 plane (level shift p - 128 applied).
+ *   form  a dct_form value.
+ *   coef  out: float [ceil(H/8) * ceil(W/8)][64], layout as dct_forward, 16-byte aligned. */
+DCT_API int dct_forward_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t form,
+                              float *coef, void *stream);
+
+/* The codec with a floating-point transform: forward in `form`, quantize
+ * q = sgn(F) floor(|F| / Q + 1/2) with the table of dct_quantize, dequantize q Q,
+ * inverse in `form`, reconstruct clamp(floor(x + 128 + 1/2), 0, 255), and the SSE
+ * against the source into *sse_dev (one uint64 in device memory, overwritten).
+ * Results are within the form's stated tolerance of the FP64 codec, not bit-exact. */
+DCT_API int dct_codec_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t form, int32_t qs,
+                            uint8_t *dst, int32_t dst_stride, uint64_t *sse_dev, void *stream);
+
+/* Integer full-range YCbCr planes of an interleaved RGB image (JFIF / BT.601 luma
+ * weights rounded to 2^-16: Y = (19595 R + 38470 G + 7471 B + 2^15) >> 16,
+ * Cb = ((-11058 R - 21710 G + 32768 B + 2^15) >> 16) + 128,
+ * Cr = ((32768 R - 27439 G - 5329 B + 2^15) >> 16) + 128, clamped to [0, 255]),
+ * so that three-channel images can be coded plane by plane.
+ *   rgb           W x H pixels of 3 bytes, row pitch rgb_stride >= 3 W.
+ *   y, cb, cr     out: W x H planes with row pitch plane_stride. */
+DCT_API int dct_rgb_to_ycbcr(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, uint8_t *y, uint8_t *cb,
+                             uint8_t *cr, int32_t plane_stride, void *stream);
+
 /* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
  * the samples, fractional bits P of the gain constants. */
 DCT_API int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits);

@@ -68,6 +68,8 @@ def lib():
         "or_recipe_quantize": (C.c_int64, [C.c_int64, C.c_int64]),
         "or_recipe_dequantize": (C.c_int64, [C.c_int64, C.c_int64]),
         "or_recipe_reconstruct": (C.c_int, [C.c_int64]),
+        "or_rgb_to_ycbcr": (None, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int]),
         "or_loeffler_forward_f64": (None, [_f64p, _f64p]),
         "or_loeffler_inverse_f64": (None, [_f64p, _f64p]),
     }
@@ -283,3 +285,16 @@ def loeffler_inverse_f64(Z) -> np.ndarray:
     out = np.empty(8, np.float64)
     lib().or_loeffler_inverse_f64(Zi, out)
     return out
+
+
+def rgb_to_ycbcr(rgb: np.ndarray):
+    """Integer full-range YCbCr planes (Y, Cb, Cr) of an (H, W, 3) uint8 RGB image."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    H, W, ch = rgb.shape
+    if ch != 3:
+        raise ValueError("expected (H, W, 3)")
+    y = np.empty((H, W), np.uint8)
+    cb = np.empty((H, W), np.uint8)
+    cr = np.empty((H, W), np.uint8)
+    lib().or_rgb_to_ycbcr(_ptr(rgb), W, H, 3 * W, _ptr(y), _ptr(cb), _ptr(cr), W)
+    return y, cb, cr

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
-from . import cordic_codec, cordic_forward, cordic_inverse, grid
+from . import cordic_codec, cordic_forward, cordic_inverse, exact_codec, grid
 
 
 def _bands(H: int, nbands: int):
@@ -66,6 +66,20 @@ def inverse_bands(qcoef: np.ndarray, qs: int, W: int, H: int, threads: int = 8) 
     def run(b):
         y0, y1, r0, r1 = b
         rec[y0:y1] = cordic_inverse(np.ascontiguousarray(qcoef[r0 * bw:r1 * bw]), qs, W, y1 - y0)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, _bands(H, threads * 4)))
+    return rec
+
+
+def exact_codec_bands(img: np.ndarray, qs: int, threads: int = 8) -> np.ndarray:
+    """The exact FP64 codec (reconstruction only), band-parallel."""
+    H, W = img.shape
+    rec = np.empty((H, W), np.uint8)
+
+    def run(b):
+        y0, y1, r0, r1 = b
+        rec[y0:y1] = exact_codec(np.ascontiguousarray(img[y0:y1]), qs)
 
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(run, _bands(H, threads * 4)))

@@ -517,6 +517,39 @@ int64_t or_recipe_dequantize(int64_t q, int64_t Q) { return recipe_dequantize(q,
 int or_recipe_reconstruct(int64_t x) { return recipe_reconstruct(x); }
 
 /* ------------------------------------------------------------------------- */
+/* Colour conversion for three-channel inputs (not in the paper, which works  */
+/* on grayscale images; the precision workload codes the Y, Cb and Cr planes  */
+/* of RGB images)                                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Integer full-range YCbCr (the JPEG File Interchange Format definition with
+ * the BT.601 luma weights 0.299, 0.587, 0.114), each weight rounded to
+ * round(w 2^16) so that the luma weights sum to 2^16 and the chroma weights to 0:
+ *   Y  = (19595 R + 38470 G +  7471 B + 2^15) >> 16
+ *   Cb = ((-11058 R - 21710 G + 32768 B + 2^15) >> 16) + 128
+ *   Cr = (( 32768 R - 27439 G -  5329 B + 2^15) >> 16) + 128
+ * (floor shifts), each clamped to [0, 255].  rgb is interleaved R, G, B bytes
+ * with row pitch rgb_stride; the three output planes share plane_stride. */
+static int clamp255(int64_t v) { return v < 0 ? 0 : (v > 255 ? 255 : (int)v); }
+
+void or_rgb_to_ycbcr(const uint8_t *rgb, int W, int H, int rgb_stride, uint8_t *y, uint8_t *cb,
+                     uint8_t *cr, int plane_stride) {
+  for (int i = 0; i < H; ++i)
+    for (int j = 0; j < W; ++j) {
+      const uint8_t *p = rgb + (int64_t)i * rgb_stride + 3 * (int64_t)j;
+      const int64_t R = p[0], G = p[1], B = p[2];
+      const int64_t half = (int64_t)1 << 15;
+      const int64_t yy = floor_div_pow2(19595 * R + 38470 * G + 7471 * B + half, 16);
+      const int64_t bb = floor_div_pow2(-11058 * R - 21710 * G + 32768 * B + half, 16) + 128;
+      const int64_t rr = floor_div_pow2(32768 * R - 27439 * G - 5329 * B + half, 16) + 128;
+      const int64_t o = (int64_t)i * plane_stride + j;
+      y[o] = (uint8_t)clamp255(yy);
+      cb[o] = (uint8_t)clamp255(bb);
+      cr[o] = (uint8_t)clamp255(rr);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* The same Loeffler graph in FP64 with exact rotations (structure pin)       */
 /* ------------------------------------------------------------------------- */
 

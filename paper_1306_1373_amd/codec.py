@@ -23,6 +23,11 @@ DCT_ERR_UNSUPPORTED = -2
 DCT_ERR_DEVICE = -3
 DCT_ERR_NOMEM = -4
 
+DCT_FORM_F32_LOEFFLER = 1
+DCT_FORM_MFMA_F16 = 2
+DCT_FORM_MFMA_BF16 = 3
+FORMS = {"f32": DCT_FORM_F32_LOEFFLER, "f16": DCT_FORM_MFMA_F16, "bf16": DCT_FORM_MFMA_BF16}
+
 # prototypes of include/dctcodec.h
 _PROTOS = {
     "dct_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -33,6 +38,12 @@ _PROTOS = {
                            C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_void_p]),
     "dct_codec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dct_forward_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_void_p, C.c_void_p]),
+    "dct_codec_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dct_rgb_to_ycbcr": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int32, C.c_void_p]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
@@ -192,6 +203,67 @@ def dct_codec(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = F
                             None if qcoef is None else qcoef.data_ptr(), sse.data_ptr(),
                             _stream(src)), "dct_codec")
     return (dst, sse, qcoef) if qcoef is not None else (dst, sse)
+
+
+def _form(form) -> int:
+    return FORMS[form] if isinstance(form, str) else int(form)
+
+
+def dct_forward_float(src, form, coef=None):
+    """Orthonormal float32 coefficients [nblocks, 64] in a floating-point form
+    ('f32' Loeffler, 'f16' or 'bf16' matrix form on the matrix cores)."""
+    import torch
+    p, W, H, s = _plane(src, "src")
+    nb = nblocks(W, H)
+    if coef is None:
+        coef = torch.empty((nb, 64), dtype=torch.float32, device=src.device)
+    if coef.dtype != torch.float32 or not coef.is_contiguous() or coef.numel() != nb * 64:
+        raise TypeError("coef must be a contiguous float32 tensor of nblocks * 64 elements")
+    _check(load().dct_forward_float(p, W, H, s, _form(form), coef.data_ptr(), _stream(src)),
+           "dct_forward_float")
+    return coef
+
+
+def dct_codec_float(src, form, qs: int, dst=None, sse=None):
+    """The codec with a floating-point transform; returns (dst, sse_tensor)."""
+    import torch
+    p, W, H, s = _plane(src, "src")
+    if dst is None:
+        dst = new_plane(W, H, src.device)
+    pd, dW, dH, ds = _plane(dst, "dst")
+    if (dW, dH) != (W, H):
+        raise ValueError("dst shape does not match src")
+    if sse is None:
+        sse = torch.empty(1, dtype=torch.int64, device=src.device)
+    _check(load().dct_codec_float(p, W, H, s, _form(form), int(qs), pd, ds, sse.data_ptr(),
+                                  _stream(src)), "dct_codec_float")
+    return dst, sse
+
+
+def dct_rgb_to_ycbcr(rgb, planes=None):
+    """(Y, Cb, Cr) uint8 planes of an (H, W, 3) uint8 RGB device tensor."""
+    import torch
+    if not isinstance(rgb, torch.Tensor) or rgb.dtype != torch.uint8 or rgb.dim() != 3 \
+            or rgb.shape[2] != 3 or not rgb.is_cuda:
+        raise TypeError("rgb must be an (H, W, 3) uint8 device tensor")
+    if rgb.stride(2) != 1 or rgb.stride(1) != 3:
+        raise TypeError("rgb pixels must be interleaved and contiguous within a row")
+    H, W, _ = rgb.shape
+    if planes is None:
+        planes = tuple(new_plane(W, H, rgb.device) for _ in range(3))
+    ptrs, strides = [], set()
+    for t in planes:
+        pt, pW, pH, ps = _plane(t, "plane")
+        if (pW, pH) != (W, H):
+            raise ValueError("plane shape does not match rgb")
+        ptrs.append(pt)
+        strides.add(ps)
+    if len(strides) != 1:
+        raise ValueError("the three planes must share one row pitch")
+    rs = rgb.stride(0) if H > 1 else 3 * W
+    _check(load().dct_rgb_to_ycbcr(rgb.data_ptr(), int(W), int(H), int(rs), *ptrs, strides.pop(),
+                                   _stream(rgb)), "dct_rgb_to_ycbcr")
+    return planes
 
 
 def psnr_from_sse(sse: int, W: int, H: int, peak: float = 255.0) -> float:

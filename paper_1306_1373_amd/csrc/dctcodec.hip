@@ -12,6 +12,7 @@
 
 #include "dctcodec.h"
 #include "kernels.hpp"
+#include "matrix_form.hpp"
 
 namespace {
 
@@ -74,6 +75,20 @@ dct::DequantTable dequant_table(int qs) {
   dct::DequantTable dq{};
   for (int s = 0; s < 15; ++s) dq.Q[s] = 1 + (1 + s) * qs;
   return dq;
+}
+
+dct::FloatQuant float_quant(int qs) {
+  dct::FloatQuant fq{};
+  for (int s = 0; s < 15; ++s) {
+    const int32_t Q = 1 + (1 + s) * qs;
+    fq.Q[s] = static_cast<float>(Q);
+    fq.rcp[s] = static_cast<float>(1.0 / Q);
+  }
+  return fq;
+}
+
+bool form_ok(int form) {
+  return form == dct::kFormF32Loeffler || form == dct::kFormMfmaF16 || form == dct::kFormMfmaBf16;
 }
 
 unsigned grid_for(int64_t items, int threads = dct::kWg) {
@@ -174,6 +189,68 @@ int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int3
   else
     dct::codec_kernel<false><<<grid, dct::kBlockThreads, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
                                                                 dst_stride, nullptr, acc);
+  return launched();
+}
+
+int dct_forward_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t form,
+                      float *coef, void *stream) {
+  if (!plane_ok(src, W, H, src_stride) || coef == nullptr || !aligned(coef, 16) || !form_ok(form))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  const int ntiles = (nblocks + 15) / 16;
+  hipStream_t s = as_stream(stream);
+  const dct::FloatQuant fq{};
+  const unsigned kgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + dct::kMfmaWaves - 1) / dct::kMfmaWaves, 4096));
+  if (form == dct::kFormF32Loeffler)
+    dct::loeffler_f32_kernel<false><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, coef,
+                                                                           fq, nullptr, 0, nullptr);
+  else if (form == dct::kFormMfmaF16)
+    dct::kron_kernel<false, false><<<kgrid, 64 * dct::kMfmaWaves, 0, s>>>(src, W, H, src_stride, bw, nblocks, ntiles,
+                                                                          coef, fq, nullptr, 0, nullptr);
+  else
+    dct::kron_kernel<true, false><<<kgrid, 64 * dct::kMfmaWaves, 0, s>>>(src, W, H, src_stride, bw, nblocks, ntiles,
+                                                                         coef, fq, nullptr, 0, nullptr);
+  return launched();
+}
+
+int dct_codec_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t form, int32_t qs,
+                    uint8_t *dst, int32_t dst_stride, uint64_t *sse_dev, void *stream) {
+  if (!plane_ok(src, W, H, src_stride) || !plane_ok(dst, W, H, dst_stride) || !form_ok(form) || qs < 1 ||
+      qs > kMaxQs || sse_dev == nullptr || !aligned(sse_dev, 8))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  const int ntiles = (nblocks + 15) / 16;
+  hipStream_t s = as_stream(stream);
+  auto *acc = reinterpret_cast<unsigned long long *>(sse_dev);
+  dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 1);
+  if (launched()) return DCT_ERR_DEVICE;
+  const dct::FloatQuant fq = float_quant(qs);
+  const unsigned kgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + dct::kMfmaWaves - 1) / dct::kMfmaWaves, 4096));
+  if (form == dct::kFormF32Loeffler)
+    dct::loeffler_f32_kernel<true><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, nullptr,
+                                                                          fq, dst, dst_stride, acc);
+  else if (form == dct::kFormMfmaF16)
+    dct::kron_kernel<false, true><<<kgrid, 64 * dct::kMfmaWaves, 0, s>>>(src, W, H, src_stride, bw, nblocks, ntiles,
+                                                                         nullptr, fq, dst, dst_stride, acc);
+  else
+    dct::kron_kernel<true, true><<<kgrid, 64 * dct::kMfmaWaves, 0, s>>>(src, W, H, src_stride, bw, nblocks, ntiles,
+                                                                        nullptr, fq, dst, dst_stride, acc);
+  return launched();
+}
+
+int dct_rgb_to_ycbcr(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, uint8_t *y, uint8_t *cb,
+                     uint8_t *cr, int32_t plane_stride, void *stream) {
+  if (rgb == nullptr || W < 1 || W > kMaxDim || H < 1 || H > kMaxDim || rgb_stride < 3 * W ||
+      static_cast<uint64_t>(H - 1) * static_cast<uint64_t>(rgb_stride) + 3u * static_cast<uint64_t>(W) >=
+          (uint64_t{1} << 32) ||
+      !plane_ok(y, W, H, plane_stride) || !plane_ok(cb, W, H, plane_stride) || !plane_ok(cr, W, H, plane_stride))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int64_t total = static_cast<int64_t>(W) * H;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(total), 8192));
+  dct::ycbcr_kernel<<<grid, dct::kWg, 0, as_stream(stream)>>>(rgb, W, H, rgb_stride, y, cb, cr, plane_stride);
   return launched();
 }
 

@@ -70,6 +70,18 @@ def synth_image(W: int, H: int, seed: int, sigma: float = 5.0) -> np.ndarray:
     return out
 
 
+def synth_rgb(W: int, H: int, seed: int, sigma: float = 5.0) -> np.ndarray:
+    """An (H, W, 3) uint8 RGB image: a luminance image from G(W, H, seed, sigma)
+    and two chroma images from G(W, H, seed + 1000, sigma) and G(W, H, seed + 2000,
+    sigma), combined as R = L + 0.3 (C1 - 128), G = L - 0.2 (C1 - 128) - 0.2 (C2 - 128),
+    B = L + 0.3 (C2 - 128), rounded half to even and clipped to [0, 255]."""
+    L = synth_image(W, H, seed, sigma).astype(np.float64)
+    c1 = synth_image(W, H, seed + 1000, sigma).astype(np.float64) - 128.0
+    c2 = synth_image(W, H, seed + 2000, sigma).astype(np.float64) - 128.0
+    rgb = np.stack([L + 0.3 * c1, L - 0.2 * c1 - 0.2 * c2, L + 0.3 * c2], axis=-1)
+    return np.clip(np.rint(rgb), 0, 255).astype(np.uint8)
+
+
 def sigma_for_seed(seed: int) -> float:
     """Noise level of the 8192 x 8192 workload: sigma = 2 + 8 s / 7 for s = 0..7."""
     return 2.0 + 8.0 * (seed % 8) / 7.0

@@ -40,12 +40,14 @@ MUTANTS = {
     # PSNR with MSE not divided by the pixel count
     "psnr_mse": ("const double mse = (double)sse / ((double)W * (double)H);",
                  "const double mse = (double)sse;"),
+    # luma weights of green and blue swapped
+    "ycbcr_weights": ("19595 * R + 38470 * G + 7471 * B", "19595 * R + 7471 * G + 38470 * B"),
     # truncating shift where the recipe floors
     "truncating_shift": ("if (v % d != 0 && v < 0) q -= 1;", "(void)0;"),
 }
 
 PIN_MODULES = ["tests/test_oracle_exact.py", "tests/test_oracle_recipe.py",
-               "tests/test_oracle_psnr.py"]
+               "tests/test_oracle_psnr.py", "tests/test_oracle_color.py"]
 
 
 def _run_pins_with(src_text, tmp_path):
