@@ -70,6 +70,15 @@ def lib():
         "or_recipe_reconstruct": (C.c_int, [C.c_int64]),
         "or_rgb_to_ycbcr": (None, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_int]),
+        "or_recipe_valid": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+        "or_recipe_tables_n": (None, [C.c_int, _intp, _i64p]),
+        "or_recipe_codec": (C.c_uint64, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int,
+                                         C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p]),
+        "or_recipe_forward_block": (C.c_int64, [C.c_int, C.c_int, C.c_int, _i64p, _i64p]),
+        "or_recipe_inverse_block": (C.c_int64, [C.c_int, C.c_int, C.c_int, _i64p, _i64p]),
+        "or_recipe_peaks": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int,
+                                      C.c_int, C.c_int, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]),
         "or_loeffler_forward_f64": (None, [_f64p, _f64p]),
         "or_loeffler_inverse_f64": (None, [_f64p, _f64p]),
     }
@@ -252,6 +261,66 @@ def cordic_inverse_block(d) -> tuple:
     x = np.empty(64, np.int64)
     peak = lib().or_cordic_inverse_block(di, x)
     return x.reshape(8, 8), int(peak)
+
+
+# ---- O7 family: recipe R(n, F, G) ------------------------------------------
+
+def _recipe_ok(n: int, F: int, G: int):
+    if not lib().or_recipe_valid(n, F, G):
+        raise ValueError(f"recipe R({n}, {F}, {G}) outside 1<=n<=16, 1<=F<=16, 1<=G<=12")
+
+
+def recipe_tables_n(n: int):
+    """(directions[3, n], gains[4]) of the recipe with n micro-rotations."""
+    _recipe_ok(n, 12, 12)
+    d = np.zeros(3 * n, np.intc)
+    g = np.zeros(4, np.int64)
+    lib().or_recipe_tables_n(n, d, g)
+    return d.reshape(3, n).astype(np.int64), g
+
+
+def recipe_codec(n: int, F: int, G: int, img: np.ndarray, qs: int, want_q: bool = False):
+    """a1..a9 under recipe R(n, F, G): (reconstruction, sse[, qcoef])."""
+    _recipe_ok(n, F, G)
+    a, W, H, _ = _plane(img)
+    src = np.ascontiguousarray(a)
+    dst = np.empty((H, W), np.uint8)
+    bw, bh = grid(W, H)
+    q = np.empty((bw * bh, 64), np.int16) if want_q else None
+    s = lib().or_recipe_codec(n, F, G, _ptr(src), W, H, W, qs, _ptr(dst), W,
+                              None if q is None else _ptr(q))
+    if s == 2**64 - 1:
+        raise MemoryError("oracle codec could not allocate")
+    return (dst, int(s), q) if want_q else (dst, int(s))
+
+
+def recipe_forward_block(n: int, F: int, G: int, x) -> tuple:
+    """Forward recipe R(n, F, G) on one block of raw fixed-point samples; (c, peak)."""
+    _recipe_ok(n, F, G)
+    xi = np.ascontiguousarray(x, dtype=np.int64).reshape(64)
+    c = np.empty(64, np.int64)
+    peak = lib().or_recipe_forward_block(n, F, G, xi, c)
+    return c.reshape(8, 8), int(peak)
+
+
+def recipe_inverse_block(n: int, F: int, G: int, d) -> tuple:
+    """Inverse recipe R(n, F, G) on one block of fixed-point coefficients; (x, peak)."""
+    _recipe_ok(n, F, G)
+    di = np.ascontiguousarray(d, dtype=np.int64).reshape(64)
+    x = np.empty(64, np.int64)
+    peak = lib().or_recipe_inverse_block(n, F, G, di, x)
+    return x.reshape(8, 8), int(peak)
+
+
+def recipe_peaks(n: int, F: int, G: int, img: np.ndarray, qs: int):
+    """(forward peak, inverse peak): the largest |value| R(n, F, G) stores on img at qs."""
+    _recipe_ok(n, F, G)
+    a, W, H, _ = _plane(img)
+    src = np.ascontiguousarray(a)
+    fp, ip = C.c_int64(), C.c_int64()
+    if lib().or_recipe_peaks(n, F, G, _ptr(src), W, H, W, qs, C.byref(fp), C.byref(ip)) != 0:
+        raise MemoryError("oracle could not allocate")
+    return int(fp.value), int(ip.value)
 
 
 def cordic_rotate(a: int, b: int, rot: int, sense: int = 1):

@@ -22,7 +22,7 @@ MUTANTS = {
     "odd_pairing": ("int64_t u4 = d3, u7 = d0, u5 = d2, u6 = d1;",
                     "int64_t u4 = d2, u7 = d1, u5 = d3, u6 = d0;"),
     # a dropped sqrt(2) on an odd output
-    "dropped_sqrt2": ("Z3 = compensate(v5, g_sqrt2), Z5", "Z3 = v5, Z5"),
+    "dropped_sqrt2": ("Z3 = compensate(v5, R->sqrt2), Z5", "Z3 = v5, Z5"),
     # a sign flip in a butterfly of the inverse
     "inverse_butterfly": ("const int64_t v7 = Z[1] + Z[7], v4 = Z[1] - Z[7];",
                           "const int64_t v7 = Z[1] - Z[7], v4 = Z[1] + Z[7];"),
@@ -30,11 +30,11 @@ MUTANTS = {
     "transposed_layout": ("for (int i = 0; i < 8; ++i) c[i * 8 + j] = t[i];",
                           "for (int i = 0; i < 8; ++i) c[j * 8 + i] = t[i];"),
     # quantizer rounding toward zero instead of to nearest
-    "quantizer_truncates": ("const int64_t m = (i64_abs(c) + (Q << (OR_FRAC + 2))) / D;",
+    "quantizer_truncates": ("const int64_t m = (i64_abs(c) + (Q << (F + 2))) / D;",
                             "const int64_t m = i64_abs(c) / D;"),
     # reconstruction without the rounding half
-    "reconstruct_floor": ("floor_div_pow2(x + ((int64_t)1 << (OR_FRAC + 2)), OR_FRAC + 3) + 128",
-                          "floor_div_pow2(x, OR_FRAC + 3) + 128"),
+    "reconstruct_floor": ("floor_div_pow2(x + ((int64_t)1 << (G + 2)), G + 3) + 128",
+                          "floor_div_pow2(x, G + 3) + 128"),
     # exact DCT with alpha indexed by position instead of frequency
     "alpha_index": ("alpha(u) * alpha(v) * s;", "alpha(0) * alpha(0) * s;"),
     # PSNR with MSE not divided by the pixel count
@@ -42,11 +42,13 @@ MUTANTS = {
                  "const double mse = (double)sse;"),
     # luma weights of green and blue swapped
     "ycbcr_weights": ("19595 * R + 38470 * G + 7471 * B", "19595 * R + 7471 * G + 38470 * B"),
+    # the forward transform scaled by the inverse's fractional bits
+    "forward_uses_G": ("((int64_t)1 << R->F);", "((int64_t)1 << R->G);"),
     # truncating shift where the recipe floors
     "truncating_shift": ("if (v % d != 0 && v < 0) q -= 1;", "(void)0;"),
 }
 
-PIN_MODULES = ["tests/test_oracle_exact.py", "tests/test_oracle_recipe.py",
+PIN_MODULES = ["tests/test_oracle_exact.py", "tests/test_oracle_recipe.py", "tests/test_oracle_recipe_family.py",
                "tests/test_oracle_psnr.py", "tests/test_oracle_color.py"]
 
 
