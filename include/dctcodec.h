@@ -69,7 +69,7 @@ extern "C" {
 typedef enum {
   DCT_OK = 0,
   DCT_ERR_INVALID = -1,     /* an argument violates the preconditions above */
-  DCT_ERR_UNSUPPORTED = -2, /* no gfx950 device is current */
+  DCT_ERR_UNSUPPORTED = -2, /* no gfx950 device is current, or the recipe is not built */
   DCT_ERR_DEVICE = -3,      /* the HIP runtime reported an error */
   DCT_ERR_NOMEM = -4        /* the library could not allocate its scratch word */
 } dct_status;
@@ -151,6 +151,31 @@ DCT_API int dct_codec_float(const uint8_t *src, int32_t W, int32_t H, int32_t sr
  *   y, cb, cr     out: W x H planes with row pitch plane_stride. */
 DCT_API int dct_rgb_to_ycbcr(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, uint8_t *y, uint8_t *cb,
                              uint8_t *cr, int32_t plane_stride, void *stream);
+
+/* The fused codec of dct_codec under another recipe R(n, F, G) of the family
+ * the paper's Sec. 2.5.2 leaves open (its flow-graph figure, with the CORDIC
+ * iteration count and word length, is missing): n micro-rotations per rotation
+ * block, F fractional bits in the forward transform (x = (p - 128) << F,
+ * coefficient = c / 2^(F+3), q = sgn(c) floor((|c| + Q 2^(F+2)) / (Q 2^(F+3)))),
+ * G in the inverse (dequantize clamp(q Q, -2048, 2047) << G, reconstruct
+ * clamp(((x + 2^(G+2)) >> (G+3)) + 128, 0, 255)); P = 15.  R(10, 12, 12) is
+ * dct_codec itself.  The library is built with n in {4, 6, 8, 10, 12} and
+ * (F, G) in {(8, 8), (12, 12), (16, 12)}; other recipes give DCT_ERR_UNSUPPORTED.
+ * Arguments and outputs as dct_codec. */
+DCT_API int dct_codec_recipe(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t n_iter,
+                             int32_t frac_bits, int32_t inv_frac_bits, int32_t qs, uint8_t *dst, int32_t dst_stride,
+                             int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
+
+/* 1 if dct_codec_recipe accepts R(n_iter, frac_bits, inv_frac_bits), else 0. */
+DCT_API int dct_recipe_supported(int32_t n_iter, int32_t frac_bits, int32_t inv_frac_bits);
+
+/* The built recipes: returns their count; when `recipes` (host) is not NULL,
+ * also writes up to `capacity` triples (n, F, G), the default first. */
+DCT_API int dct_recipe_list(int32_t *recipes, int32_t capacity);
+
+/* Constants of the built recipes with n_iter micro-rotations (host outs), as
+ * dct_recipe_tables; DCT_ERR_UNSUPPORTED if no built recipe has that n. */
+DCT_API int dct_recipe_tables_n(int32_t n_iter, int32_t *directions, int32_t *gains);
 
 /* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
  * the samples, fractional bits P of the gain constants. */

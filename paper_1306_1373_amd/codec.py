@@ -44,6 +44,12 @@ _PROTOS = {
                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dct_rgb_to_ycbcr": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_int32, C.c_void_p]),
+    "dct_codec_recipe": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "dct_recipe_supported": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
+    "dct_recipe_list": (C.c_int, [C.POINTER(C.c_int32), C.c_int32]),
+    "dct_recipe_tables_n": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
@@ -185,6 +191,16 @@ def dct_psnr(a, b, peak: float = 255.0):
 def dct_codec(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
     """a1-a9 in one pass.  Returns (dst, sse_tensor) or (dst, sse_tensor, qcoef);
     sse_tensor is a one-element int64 device tensor holding the uint64 SSE."""
+    return _codec(src, qs, dst, qcoef, sse, want_qcoef, None)
+
+
+def dct_codec_recipe(src, recipe, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
+    """dct_codec under recipe (n, F, G); returns as dct_codec."""
+    n, F, G = (int(v) for v in recipe)
+    return _codec(src, qs, dst, qcoef, sse, want_qcoef, (n, F, G))
+
+
+def _codec(src, qs, dst, qcoef, sse, want_qcoef, recipe):
     import torch
     p, W, H, s = _plane(src, "src")
     if dst is None:
@@ -199,9 +215,13 @@ def dct_codec(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = F
         raise TypeError("qcoef must be a contiguous int16 tensor matching the block grid")
     if sse is None:
         sse = torch.empty(1, dtype=torch.int64, device=src.device)
-    _check(load().dct_codec(p, W, H, s, int(qs), pd, ds,
-                            None if qcoef is None else qcoef.data_ptr(), sse.data_ptr(),
-                            _stream(src)), "dct_codec")
+    qptr = None if qcoef is None else qcoef.data_ptr()
+    if recipe is None:
+        _check(load().dct_codec(p, W, H, s, int(qs), pd, ds, qptr, sse.data_ptr(), _stream(src)),
+               "dct_codec")
+    else:
+        _check(load().dct_codec_recipe(p, W, H, s, *recipe, int(qs), pd, ds, qptr, sse.data_ptr(),
+                                       _stream(src)), "dct_codec_recipe")
     return (dst, sse, qcoef) if qcoef is not None else (dst, sse)
 
 
@@ -280,12 +300,31 @@ def recipe_info():
     return n.value, f.value, p.value
 
 
-def recipe_tables():
-    n = recipe_info()[0]
-    d = (C.c_int32 * (3 * n))()
-    g = (C.c_int32 * 4)()
-    _check(load().dct_recipe_tables(d, g), "dct_recipe_tables")
+def recipe_tables(n: int = None):
+    """(directions[3][n], gains[4]) of the default recipe, or of the built recipes with n."""
+    if n is None:
+        n = recipe_info()[0]
+        d = (C.c_int32 * (3 * n))()
+        g = (C.c_int32 * 4)()
+        _check(load().dct_recipe_tables(d, g), "dct_recipe_tables")
+    else:
+        d = (C.c_int32 * (3 * n))()
+        g = (C.c_int32 * 4)()
+        _check(load().dct_recipe_tables_n(int(n), d, g), "dct_recipe_tables_n")
     return [[d[r * n + i] for i in range(n)] for r in range(3)], list(g)
+
+
+def recipe_list():
+    """The built recipes as (n, F, G) triples, the default first."""
+    L = load()
+    count = L.dct_recipe_list(None, 0)
+    buf = (C.c_int32 * (3 * count))()
+    L.dct_recipe_list(buf, count)
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(count)]
+
+
+def recipe_supported(n: int, F: int, G: int) -> bool:
+    return bool(load().dct_recipe_supported(int(n), int(F), int(G)))
 
 
 def status_string(status: int) -> str:

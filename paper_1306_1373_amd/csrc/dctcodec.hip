@@ -55,21 +55,82 @@ int check_device(int *dev_out) {
 
 int launched() { return hipGetLastError() == hipSuccess ? DCT_OK : DCT_ERR_DEVICE; }
 
-// Quantizer of the fused codec for Q[u][v] = 1 + (1 + u + v) qs, indexed by u + v:
-// the smallest float r >= 1/Q makes trunc(float(m) r) = floor(m / Q) for every
-// m < 2^14 (the lemma the CPU tests check for every table entry).
-dct::CodecQuant codec_quant(int qs) {
+// Quantizer of the fused codec for Q[u][v] = 1 + (1 + u + v) qs, indexed by u + v,
+// under F forward and G inverse fractional bits: the smallest float r >= 1/Q
+// makes trunc(float(m) r) = floor(m / Q) for every m < 2^14 (the lemma the CPU
+// tests check for every table entry); half is the rounding offset after the
+// pre-shift max(F - 12, 0).
+dct::CodecQuant codec_quant(int qs, int F, int G) {
   dct::CodecQuant qa{};
+  const int pre = F > 12 ? F - 12 : 0;
   for (int s = 0; s < 15; ++s) {
     const int32_t Q = 1 + (1 + s) * qs;
     float r = static_cast<float>(1.0 / Q);
     if (static_cast<double>(r) < 1.0 / Q) r = std::nextafter(r, std::numeric_limits<float>::infinity());
     qa.rcp[s] = r;
-    qa.qscale[s] = static_cast<float>(Q) * static_cast<float>(1 << dct::kFrac);
-    qa.half[s] = Q << (dct::kFrac + 2);
+    qa.qscale[s] = static_cast<float>(Q) * static_cast<float>(1 << G);
+    qa.half[s] = Q << (F + 2 - pre);
   }
   return qa;
 }
+
+// The fused codec under one recipe.
+struct CodecArgs {
+  const uint8_t *src;
+  int W, H, src_stride, bw, nblocks;
+  dct::CodecQuant qa;
+  uint8_t *dst;
+  int dst_stride;
+  int16_t *qcoef;
+  unsigned long long *sse;
+};
+
+template <class RC>
+void launch_codec(const CodecArgs &a, hipStream_t s) {
+  const unsigned grid = static_cast<unsigned>((a.nblocks + dct::kBlockThreads - 1) / dct::kBlockThreads);
+  if (a.qcoef)
+    dct::codec_kernel<RC, true><<<grid, dct::kBlockThreads, 0, s>>>(a.src, a.W, a.H, a.src_stride, a.bw, a.nblocks,
+                                                                   a.qa, a.dst, a.dst_stride, a.qcoef, a.sse);
+  else
+    dct::codec_kernel<RC, false><<<grid, dct::kBlockThreads, 0, s>>>(a.src, a.W, a.H, a.src_stride, a.bw, a.nblocks,
+                                                                    a.qa, a.dst, a.dst_stride, nullptr, a.sse);
+}
+
+struct RecipeEntry {
+  int n, F, G;
+  void (*launch)(const CodecArgs &, hipStream_t);
+  void (*tables)(int32_t *, int32_t *);
+};
+
+template <int N>
+void copy_tables(int32_t *directions, int32_t *gains) {
+  for (int r = 0; r < 3; ++r)
+    for (int i = 0; i < N; ++i) directions[r * N + i] = dct::kTablesN<N>.dir[r][i];
+  for (int r = 0; r < 3; ++r) gains[r] = dct::kTablesN<N>.gain[r];
+  gains[3] = dct::kTablesN<N>.sqrt2;
+}
+
+template <int N, int F, int G>
+constexpr RecipeEntry entry() {
+  return {N, F, G, &launch_codec<dct::Recipe<N, F, G>>, &copy_tables<N>};
+}
+
+// The recipes the library is built with: n in {4, 6, 8, 10, 12} micro-rotations,
+// (F, G) in {(8, 8), (12, 12), (16, 12)}.  The first is the default.
+constexpr RecipeEntry kRecipes[] = {
+    entry<10, 12, 12>(), entry<4, 8, 8>(),   entry<4, 12, 12>(), entry<4, 16, 12>(), entry<6, 8, 8>(),
+    entry<6, 12, 12>(),  entry<6, 16, 12>(), entry<8, 8, 8>(),   entry<8, 12, 12>(), entry<8, 16, 12>(),
+    entry<10, 8, 8>(),   entry<10, 16, 12>(), entry<12, 8, 8>(), entry<12, 12, 12>(), entry<12, 16, 12>(),
+};
+
+const RecipeEntry *find_recipe(int n, int F, int G) {
+  for (const RecipeEntry &r : kRecipes)
+    if (r.n == n && r.F == F && r.G == G) return &r;
+  return nullptr;
+}
+
+int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, const RecipeEntry &rc, int32_t qs,
+                 uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
 
 dct::DequantTable dequant_table(int qs) {
   dct::DequantTable dq{};
@@ -175,21 +236,45 @@ int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int3
       sse_dev == nullptr || !aligned(sse_dev, 8) ||
       (qcoef_or_null != nullptr && !aligned(qcoef_or_null, 16)))
     return DCT_ERR_INVALID;
-  if (int st = check_device(nullptr)) return st;
-  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
-  hipStream_t s = as_stream(stream);
-  auto *acc = reinterpret_cast<unsigned long long *>(sse_dev);
-  dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 1);
-  if (launched()) return DCT_ERR_DEVICE;
-  const dct::CodecQuant qa = codec_quant(qs);
-  const unsigned grid = grid_for(nblocks, dct::kBlockThreads);
-  if (qcoef_or_null)
-    dct::codec_kernel<true><<<grid, dct::kBlockThreads, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
-                                                               dst_stride, qcoef_or_null, acc);
-  else
-    dct::codec_kernel<false><<<grid, dct::kBlockThreads, 0, s>>>(src, W, H, src_stride, bw, nblocks, qa, dst,
-                                                                dst_stride, nullptr, acc);
-  return launched();
+  return codec_common(src, W, H, src_stride, kRecipes[0], qs, dst, dst_stride, qcoef_or_null, sse_dev, stream);
+}
+
+int dct_codec_recipe(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t n_iter,
+                     int32_t frac_bits, int32_t inv_frac_bits, int32_t qs, uint8_t *dst, int32_t dst_stride,
+                     int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+  if (!plane_ok(src, W, H, src_stride) || !plane_ok(dst, W, H, dst_stride) || qs < 1 || qs > kMaxQs ||
+      sse_dev == nullptr || !aligned(sse_dev, 8) ||
+      (qcoef_or_null != nullptr && !aligned(qcoef_or_null, 16)))
+    return DCT_ERR_INVALID;
+  const RecipeEntry *rc = find_recipe(n_iter, frac_bits, inv_frac_bits);
+  if (rc == nullptr) return DCT_ERR_UNSUPPORTED;
+  return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream);
+}
+
+int dct_recipe_supported(int32_t n_iter, int32_t frac_bits, int32_t inv_frac_bits) {
+  return find_recipe(n_iter, frac_bits, inv_frac_bits) != nullptr ? 1 : 0;
+}
+
+int dct_recipe_list(int32_t *recipes, int32_t capacity) {
+  const int count = static_cast<int>(sizeof(kRecipes) / sizeof(kRecipes[0]));
+  if (recipes == nullptr) return count;
+  if (capacity < 0) return DCT_ERR_INVALID;
+  for (int i = 0; i < count && i < capacity; ++i) {
+    recipes[3 * i] = kRecipes[i].n;
+    recipes[3 * i + 1] = kRecipes[i].F;
+    recipes[3 * i + 2] = kRecipes[i].G;
+  }
+  return count;
+}
+
+int dct_recipe_tables_n(int32_t n_iter, int32_t *directions, int32_t *gains) {
+  if (directions == nullptr || gains == nullptr) return DCT_ERR_INVALID;
+  for (const RecipeEntry &r : kRecipes)
+    if (r.n == n_iter) {
+      r.tables(directions, gains);
+      return DCT_OK;
+    }
+  return DCT_ERR_UNSUPPORTED;
 }
 
 int dct_forward_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t form,
@@ -262,20 +347,13 @@ int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits) {
   return DCT_OK;
 }
 
-int dct_recipe_tables(int32_t *directions, int32_t *gains) {
-  if (directions == nullptr || gains == nullptr) return DCT_ERR_INVALID;
-  for (int r = 0; r < 3; ++r)
-    for (int i = 0; i < dct::kIter; ++i) directions[r * dct::kIter + i] = dct::kTables.dir[r][i];
-  for (int r = 0; r < 3; ++r) gains[r] = dct::kTables.gain[r];
-  gains[3] = dct::kTables.sqrt2;
-  return DCT_OK;
-}
+int dct_recipe_tables(int32_t *directions, int32_t *gains) { return dct_recipe_tables_n(dct::kIter, directions, gains); }
 
 const char *dct_status_string(int status) {
   switch (status) {
     case DCT_OK: return "ok";
     case DCT_ERR_INVALID: return "invalid argument";
-    case DCT_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+    case DCT_ERR_UNSUPPORTED: return "unsupported device (gfx950 required) or recipe not built";
     case DCT_ERR_DEVICE: return "HIP runtime error";
     case DCT_ERR_NOMEM: return "out of device memory";
     default: return "unknown status";
@@ -295,3 +373,29 @@ int dct_shutdown(void) {
 }
 
 }  // extern "C"
+
+namespace {
+
+int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, const RecipeEntry &rc, int32_t qs,
+                 uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+  if (int st = check_device(nullptr)) return st;
+  CodecArgs a{};
+  a.src = src;
+  a.W = W;
+  a.H = H;
+  a.src_stride = src_stride;
+  a.bw = (W + 7) / 8;
+  a.nblocks = a.bw * ((H + 7) / 8);
+  a.qa = codec_quant(qs, rc.F, rc.G);
+  a.dst = dst;
+  a.dst_stride = dst_stride;
+  a.qcoef = qcoef_or_null;
+  a.sse = reinterpret_cast<unsigned long long *>(sse_dev);
+  hipStream_t s = as_stream(stream);
+  dct::fill_zero_kernel<<<1, 64, 0, s>>>(a.sse, 1);
+  if (launched()) return DCT_ERR_DEVICE;
+  rc.launch(a, s);
+  return launched();
+}
+
+}  // namespace

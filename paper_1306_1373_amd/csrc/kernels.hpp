@@ -24,15 +24,20 @@
 //   * The level shift x = (p - 128) 2^F only changes the DC coefficient: in the
 //     graph a constant added to all eight inputs reaches Z0 alone, through
 //     butterflies only.  The kernels transform p 2^F and subtract
-//     64 * 128 * 2^F = 2^25 from the DC coefficient.
-//   * Likewise the reconstruction's + 2^(F+2) rounding and + 128 level shift,
-//     added to every output, equal adding 2^(F+2) + 2^(F+10) to the
+//     64 * 128 * 2^F = 2^(F+13) from the DC coefficient.
+//   * Likewise the reconstruction's + 2^(G+2) rounding and + 128 level shift,
+//     added to every output, equal adding 2^(G+2) + 2^(G+10) to the
 //     dequantized DC coefficient before the inverse.
-//   * The fused kernel's quantizer divides m = (|c| + Q 2^(F+2)) >> (F+3)
-//     (m < 2^14) by Q as trunc(float(m) * r) with r the smallest float >= 1/Q,
-//     exact for every table entry and m (checked exhaustively on the CPU);
-//     it omits the dequantization clamp, which no coefficient of a uint8 block
-//     can reach (|qQ| <= 2041; also checked on the CPU).
+//   * The fused kernel's quantizer forms m = (|c| + Q 2^(F+2)) >> (F+3) as
+//     ((|c| >> s) + Q 2^(F+2-s)) >> (F+3-s) with s = max(F - 12, 0), equal
+//     because Q 2^(F+2) is a multiple of 2^s, and which keeps the sum inside
+//     32 bits; it divides m (< 2^14) by Q as trunc(float(m) * r) with r the
+//     smallest float >= 1/Q, exact for every table entry and m (checked
+//     exhaustively on the CPU); it omits the dequantization clamp, which no
+//     coefficient of a uint8 block can reach (|qQ| <= 2041; also checked).
+//
+// The staged kernels run the default recipe R(10, 12, 12); the fused codec
+// kernel is instantiated for each recipe R(n, F, G) the library offers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,9 +54,13 @@ inline constexpr int kWg = 256;            // workgroup of the elementwise kerne
 // Quantizer of the fused codec, indexed by s = u + v (0..14), wave-uniform (SGPRs).
 struct CodecQuant {
   float rcp[15];     // smallest float >= 1/Q
-  float qscale[15];  // Q 2^F (exact in float)
-  int32_t half[15];  // Q 2^(F+2), the quantizer's rounding offset
+  float qscale[15];  // Q 2^G (exact in float)
+  int32_t half[15];  // Q 2^(F+2-s), the quantizer's rounding offset after the pre-shift s
 };
+
+// pre-shift of the fused quantizer: s = max(F - 12, 0)
+template <int F>
+inline constexpr int kQuantPreShift = F > 12 ? F - 12 : 0;
 
 // Dequantizer of the staged inverse: the table entries Q, indexed by s = u + v.
 struct DequantTable {
@@ -97,34 +106,40 @@ __device__ __forceinline__ void load_block(const uint8_t *__restrict__ src, int 
 }
 
 // x = p 2^F for every pixel (the level shift is applied on DC afterwards)
+template <int F>
 __device__ __forceinline__ void unpack_block(const uint32_t (&pix)[16], int (&x)[64]) {
+  static_assert(F >= 8 && F <= 16, "byte lanes are shifted into place");
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const uint32_t w = pix[k];
-    x[4 * k + 0] = static_cast<int>((w << kFrac) & (0xffu << kFrac));
-    x[4 * k + 1] = static_cast<int>((w << (kFrac - 8)) & (0xffu << kFrac));
-    x[4 * k + 2] = static_cast<int>((w >> (16 - kFrac)) & (0xffu << kFrac));
-    x[4 * k + 3] = static_cast<int>((w >> (24 - kFrac)) & (0xffu << kFrac));
+    x[4 * k + 0] = static_cast<int>((w << F) & (0xffu << F));
+    x[4 * k + 1] = static_cast<int>((w << (F - 8)) & (0xffu << F));
+    x[4 * k + 2] = static_cast<int>((w >> (16 - F)) & (0xffu << F));
+    x[4 * k + 3] = static_cast<int>((w >> (24 - F)) & (0xffu << F));
   }
 }
 
-inline constexpr int kLevelShiftDC = 64 * 128 * (1 << kFrac);                    // 2^25
-inline constexpr int kReconstructDC = (1 << (kFrac + 2)) + (128 << (kFrac + 3));  // 2^14 + 2^22
+template <int F>
+inline constexpr int kLevelShiftDC = 64 * 128 * (1 << F);  // 2^(F+13)
+template <int G>
+inline constexpr int kReconstructDC = (1 << (G + 2)) + (128 << (G + 3));  // 2^(G+2) + 2^(G+10)
 
 // a1..a4 on a register block: transform of p 2^F, then the level shift on DC
+template <int N, int F>
 __device__ __forceinline__ void forward_block(int (&x)[64]) {
-  forward_pass<true>(x);
+  forward_pass<N, true>(x);
   barrier();
-  forward_pass<false>(x);
-  x[0] -= kLevelShiftDC;
+  forward_pass<N, false>(x);
+  x[0] -= kLevelShiftDC<F>;
 }
 
-// a7 on a register block of dequantized values d 2^F; the caller has already
-// added kReconstructDC to the DC value
+// a7 on a register block of dequantized values d 2^G; the caller has already
+// added kReconstructDC<G> to the DC value
+template <int N>
 __device__ __forceinline__ void inverse_block(int (&x)[64]) {
-  inverse_pass<false>(x);
+  inverse_pass<N, false>(x);
   barrier();
-  inverse_pass<true>(x);
+  inverse_pass<N, true>(x);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,10 +147,12 @@ __device__ __forceinline__ void inverse_block(int (&x)[64]) {
 // ---------------------------------------------------------------------------
 
 // Fused-codec quantizer for a coefficient c of a uint8 block in table slot s:
-// returns the dequantized value d 2^F and, through q_out, q itself.
+// returns the dequantized value d 2^G and, through q_out, q itself.
+template <int F>
 __device__ __forceinline__ int quant_dequant(int c, float rcp, float qscale, int32_t half, int &q_out) {
-  const int a = max(c, -c);
-  const uint32_t m = static_cast<uint32_t>(a + half) >> (kFrac + 3);
+  constexpr int s = kQuantPreShift<F>;
+  const int a = max(c, -c) >> s;
+  const uint32_t m = static_cast<uint32_t>(a + half) >> (F + 3 - s);
   const float qf = __builtin_truncf(static_cast<float>(m) * rcp);
   const int d = static_cast<int>(static_cast<uint32_t>(qf * qscale));
   const int sgn = c >> 31;
@@ -164,14 +181,15 @@ __device__ __forceinline__ int quantize_any(int c, int32_t Q) {
 // a8: reconstruction, packing, storing
 // ---------------------------------------------------------------------------
 
-// p = clamp(x >> (F+3), 0, 255) for x that already carries the rounding and +128
+// p = clamp(x >> (G+3), 0, 255) for x that already carries the rounding and +128
+template <int G>
 __device__ __forceinline__ void pack_block(const int (&x)[64], uint32_t (&rec)[16]) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     uint32_t w = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      w |= static_cast<uint32_t>(min(max(x[4 * k + j] >> (kFrac + 3), 0), 255)) << (8 * j);
+      w |= static_cast<uint32_t>(min(max(x[4 * k + j] >> (G + 3), 0), 255)) << (8 * j);
     rec[k] = w;
   }
 }
@@ -287,9 +305,9 @@ __global__ __launch_bounds__(kBlockThreads) void forward_kernel(const uint8_t *_
   uint32_t pix[16] = {};
   if (p.live) load_block(src, W, H, stride, p.by, p.bx, p.full, pix);
   int x[64];
-  unpack_block(pix, x);
+  unpack_block<kFrac>(pix, x);
   barrier();
-  forward_block(x);
+  forward_block<kIter, kFrac>(x);
   if (p.live) {
     int4 *out = reinterpret_cast<int4 *>(coef + static_cast<size_t>(b) * 64);
 #pragma unroll
@@ -349,18 +367,18 @@ __global__ __launch_bounds__(kBlockThreads) void inverse_kernel(const int16_t *_
       const int d = __mul24(x[u * 8 + v], dq.Q[u + v]);
       x[u * 8 + v] = min(max(d, -2048), 2047) * (1 << kFrac);
     }
-  x[0] += kReconstructDC;
+  x[0] += kReconstructDC<kFrac>;
   barrier();
-  inverse_block(x);
+  inverse_block<kIter>(x);
   uint32_t rec[16];
-  pack_block(x, rec);
+  pack_block<kFrac>(x, rec);
   if (p.live) store_block(dst, W, H, stride, p.by, p.bx, p.full, rec);
 }
 
-// a1..a9 fused: one lane per block; only pixels (and optionally the int16
-// quantized values) touch memory; the SSE goes to *sse by one atomic per
-// workgroup.
-template <bool kEmitQ>
+// a1..a9 fused under recipe RC: one lane per block; only pixels (and optionally
+// the int16 quantized values) touch memory; the SSE goes to *sse by one atomic
+// per workgroup.
+template <class RC, bool kEmitQ>
 __global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__restrict__ src, int W, int H,
                                                               int src_stride, int bw, int nblocks, CodecQuant qa,
                                                               uint8_t *__restrict__ dst, int dst_stride,
@@ -371,9 +389,9 @@ __global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__r
   uint32_t pix[16] = {};
   if (p.live) load_block(src, W, H, src_stride, p.by, p.bx, p.full, pix);
   int x[64];
-  unpack_block(pix, x);
+  unpack_block<RC::frac>(pix, x);
   barrier();
-  forward_block(x);
+  forward_block<RC::n, RC::frac>(x);
   barrier();
   int q[64];
 #pragma unroll
@@ -381,7 +399,7 @@ __global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__r
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int s = u + v;
-      x[u * 8 + v] = quant_dequant(x[u * 8 + v], qa.rcp[s], qa.qscale[s], qa.half[s], q[u * 8 + v]);
+      x[u * 8 + v] = quant_dequant<RC::frac>(x[u * 8 + v], qa.rcp[s], qa.qscale[s], qa.half[s], q[u * 8 + v]);
     }
   if constexpr (kEmitQ) {
     if (p.live) {
@@ -392,12 +410,12 @@ __global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__r
                            (q[8 * k + 4] & 0xffff) | (q[8 * k + 5] << 16), (q[8 * k + 6] & 0xffff) | (q[8 * k + 7] << 16));
     }
   }
-  x[0] += kReconstructDC;
+  x[0] += kReconstructDC<RC::inv_frac>;
   barrier();
-  inverse_block(x);
+  inverse_block<RC::n>(x);
   barrier();
   uint32_t rec[16];
-  pack_block(x, rec);
+  pack_block<RC::inv_frac>(x, rec);
   uint32_t err = 0;
   if (p.live) {
     store_block(dst, W, H, dst_stride, p.by, p.bx, p.full, rec);

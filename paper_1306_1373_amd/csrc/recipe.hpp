@@ -3,9 +3,11 @@
 // The Loeffler 8-point flow graph (Sec. 2.5.2) has three rotation blocks, by
 // pi/16, 3pi/16 and 6pi/16; the last one also carries a factor sqrt(2), and two
 // odd outputs are scaled by sqrt(2).  Each rotation block is computed as
-// kIter CORDIC micro-rotations
+// n CORDIC micro-rotations
 //     a' = a + d_i (b >> i),   b' = b - d_i (a >> i)
-// followed by one gain-compensation multiply (v M + 2^(P-1)) >> P.
+// followed by one gain-compensation multiply (v M + 2^(P-1)) >> P.  A recipe
+// R(n, F, G) also fixes F, the fractional bits of the forward transform's
+// samples, and G, those of the inverse's; the default is R(10, 12, 12).
 //
 // Everything here is derived at compile time from first principles so that the
 // kernels carry the directions and gains as immediates:
@@ -22,9 +24,10 @@
 
 namespace dct {
 
-inline constexpr int kIter = 10;  // CORDIC micro-rotations per rotation block (n)
-inline constexpr int kFrac = 12;  // fractional bits of the fixed-point samples (F)
-inline constexpr int kComp = 15;  // fractional bits of the gain constants (P)
+inline constexpr int kIter = 10;     // default CORDIC micro-rotations per rotation block (n)
+inline constexpr int kFrac = 12;     // default fractional bits of the samples (F = G)
+inline constexpr int kComp = 15;     // fractional bits of the gain constants (P)
+inline constexpr int kMaxIter = 16;
 
 namespace detail {
 
@@ -70,21 +73,24 @@ constexpr int32_t round_pos(double v) { return static_cast<int32_t>(v + 0.5); }
 // rotation blocks of the graph
 enum Rot : int { kRot1 = 0, kRot3 = 1, kRot6 = 2 };
 
+template <int N>
 struct Tables {
-  int dir[3][kIter];  // CORDIC directions of the pi/16, 3pi/16, 6pi/16 blocks
-  int32_t gain[3];    // M of each block; the 6pi/16 block includes sqrt(2)
-  int32_t sqrt2;      // round(sqrt(2) 2^P) for the odd sqrt(2) factors
+  int dir[3][N];    // CORDIC directions of the pi/16, 3pi/16, 6pi/16 blocks
+  int32_t gain[3];  // M of each block; the 6pi/16 block includes sqrt(2)
+  int32_t sqrt2;    // round(sqrt(2) 2^P) for the odd sqrt(2) factors
 };
 
-constexpr Tables make_tables() {
-  Tables t{};
+template <int N>
+constexpr Tables<N> make_tables() {
+  static_assert(N >= 1 && N <= kMaxIter, "micro-rotation count");
+  Tables<N> t{};
   const double theta[3] = {detail::kPi / 16.0, 3.0 * detail::kPi / 16.0, 6.0 * detail::kPi / 16.0};
   const double k[3] = {1.0, 1.0, detail::sqrt_newton(2.0)};
   double K = 1.0;
-  for (int i = 0; i < kIter; ++i) K *= detail::sqrt_newton(1.0 + detail::pow2(-2 * i));
+  for (int i = 0; i < N; ++i) K *= detail::sqrt_newton(1.0 + detail::pow2(-2 * i));
   for (int r = 0; r < 3; ++r) {
     double z = theta[r];
-    for (int i = 0; i < kIter; ++i) {
+    for (int i = 0; i < N; ++i) {
       const int d = z >= 0.0 ? 1 : -1;
       t.dir[r][i] = d;
       z -= d * detail::atan_pow2(i);
@@ -95,11 +101,29 @@ constexpr Tables make_tables() {
   return t;
 }
 
-inline constexpr Tables kTables = make_tables();
+template <int N>
+inline constexpr Tables<N> kTablesN = make_tables<N>();
+
+inline constexpr Tables<kIter> kTables = kTablesN<kIter>;
+
+// A recipe R(n, F, G).  F and G bound what int32 holds: the forward transform
+// of p 2^F stores at most 2^(F + 14) (the DC path of a 255 block) and the
+// inverse of clamped dequantized values at most 2^(G + 16.9).
+template <int N, int F, int G>
+struct Recipe {
+  static constexpr int n = N;
+  static constexpr int frac = F;
+  static constexpr int inv_frac = G;
+  static_assert(F >= 8 && F <= 16, "forward fractional bits");
+  static_assert(G >= 8 && G <= 12, "inverse fractional bits");
+};
+
+using DefaultRecipe = Recipe<kIter, kFrac, kFrac>;
 
 // the gains stay within the operand range the kernels rely on
 static_assert(kTables.gain[kRot1] > 0 && kTables.gain[kRot1] < (1 << 16), "gain range");
 static_assert(kTables.gain[kRot6] > 0 && kTables.gain[kRot6] < (1 << 16), "gain range");
 static_assert(kTables.sqrt2 > 0 && kTables.sqrt2 < (1 << 16), "gain range");
+static_assert(kTablesN<4>.gain[kRot6] < (1 << 16) && kTablesN<16>.gain[kRot1] > 0, "gain range");
 
 }  // namespace dct

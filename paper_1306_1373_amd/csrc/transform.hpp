@@ -12,7 +12,7 @@
 // The inverse graph is the transpose: the stages in reverse order with every
 // rotation by -t.
 //
-// Every rotation block is kIter micro-rotations a' = a + d_i (b >> i),
+// Every rotation block is N micro-rotations a' = a + d_i (b >> i),
 // b' = b - d_i (a >> i), directions resolved at compile time, followed by the
 // gain compensation (v M + 2^(P-1)) >> P of each output.  All shifts are
 // arithmetic; no value leaves int32 (the largest magnitude any step stores is
@@ -36,9 +36,9 @@ namespace dct {
 __device__ __forceinline__ void region() { __builtin_amdgcn_sched_barrier(0); }
 
 // one micro-rotation step I of rotation block R; S = +1 rotates by +theta, -1 by -theta
-template <int R, int S, int I>
+template <int N, int R, int S, int I>
 __device__ __forceinline__ void cordic_step(int &a, int &b) {
-  constexpr int d = S * kTables.dir[R][I];
+  constexpr int d = S * kTablesN<N>.dir[R][I];
   const int sa = a >> I;
   const int sb = b >> I;
   if constexpr (d > 0) {
@@ -57,31 +57,32 @@ __device__ __forceinline__ int compensate(int v) {
 }
 
 // the micro-rotations of the three rotation blocks of all eight lines, step by step
-template <int S, int I = 0>
+template <int N, int S, int I = 0>
 __device__ __forceinline__ void cordic_lines(int (&a1)[8], int (&b1)[8], int (&a3)[8], int (&b3)[8],
                                              int (&a6)[8], int (&b6)[8]) {
-  if constexpr (I < kIter) {
+  if constexpr (I < N) {
 #pragma unroll
     for (int L = 0; L < 8; ++L) {
-      cordic_step<kRot1, S, I>(a1[L], b1[L]);
-      cordic_step<kRot3, S, I>(a3[L], b3[L]);
-      cordic_step<kRot6, S, I>(a6[L], b6[L]);
+      cordic_step<N, kRot1, S, I>(a1[L], b1[L]);
+      cordic_step<N, kRot3, S, I>(a3[L], b3[L]);
+      cordic_step<N, kRot6, S, I>(a6[L], b6[L]);
     }
-    cordic_lines<S, I + 1>(a1, b1, a3, b3, a6, b6);
+    cordic_lines<N, S, I + 1>(a1, b1, a3, b3, a6, b6);
   }
 }
 
 // the gain compensations of the three rotation blocks of all eight lines
+template <int N>
 __device__ __forceinline__ void gains_lines(int (&a1)[8], int (&b1)[8], int (&a3)[8], int (&b3)[8],
                                             int (&a6)[8], int (&b6)[8]) {
 #pragma unroll
   for (int L = 0; L < 8; ++L) {
-    a1[L] = compensate<kTables.gain[kRot1]>(a1[L]);
-    b1[L] = compensate<kTables.gain[kRot1]>(b1[L]);
-    a3[L] = compensate<kTables.gain[kRot3]>(a3[L]);
-    b3[L] = compensate<kTables.gain[kRot3]>(b3[L]);
-    a6[L] = compensate<kTables.gain[kRot6]>(a6[L]);
-    b6[L] = compensate<kTables.gain[kRot6]>(b6[L]);
+    a1[L] = compensate<kTablesN<N>.gain[kRot1]>(a1[L]);
+    b1[L] = compensate<kTablesN<N>.gain[kRot1]>(b1[L]);
+    a3[L] = compensate<kTablesN<N>.gain[kRot3]>(a3[L]);
+    b3[L] = compensate<kTablesN<N>.gain[kRot3]>(b3[L]);
+    a6[L] = compensate<kTablesN<N>.gain[kRot6]>(a6[L]);
+    b6[L] = compensate<kTablesN<N>.gain[kRot6]>(b6[L]);
   }
 }
 
@@ -92,7 +93,7 @@ __device__ __forceinline__ int &at(int (&x)[64], int line, int k) {
 }
 
 // forward graph on the eight rows (kRows) or columns of a block, in place
-template <bool kRows>
+template <int N, bool kRows>
 __device__ __forceinline__ void forward_pass(int (&x)[64]) {
   int e0[8], e1[8], a6[8], b6[8], a3[8], b3[8], a1[8], b1[8];
 #pragma unroll
@@ -113,9 +114,9 @@ __device__ __forceinline__ void forward_pass(int (&x)[64]) {
     a1[L] = d2;       // (u5, u6) = R(d2, d1; pi/16)
     b1[L] = d1;
   }
-  cordic_lines<+1>(a1, b1, a3, b3, a6, b6);
+  cordic_lines<N, +1>(a1, b1, a3, b3, a6, b6);
   region();
-  gains_lines(a1, b1, a3, b3, a6, b6);
+  gains_lines<N>(a1, b1, a3, b3, a6, b6);
   region();
   int v5[8], v6[8];
 #pragma unroll
@@ -136,21 +137,21 @@ __device__ __forceinline__ void forward_pass(int (&x)[64]) {
   // stage 4, the two sqrt(2) factors
 #pragma unroll
   for (int L = 0; L < 8; ++L) {
-    at<kRows>(x, L, 3) = compensate<kTables.sqrt2>(v5[L]);
-    at<kRows>(x, L, 5) = compensate<kTables.sqrt2>(v6[L]);
+    at<kRows>(x, L, 3) = compensate<kTablesN<N>.sqrt2>(v5[L]);
+    at<kRows>(x, L, 5) = compensate<kTablesN<N>.sqrt2>(v6[L]);
   }
   region();
 }
 
 // inverse (transposed) graph on the eight columns or rows of a block, in place
-template <bool kRows>
+template <int N, bool kRows>
 __device__ __forceinline__ void inverse_pass(int (&x)[64]) {
   // stage 4 transposed: v5 = sqrt2 Z3, v6 = sqrt2 Z5
   int v5[8], v6[8];
 #pragma unroll
   for (int L = 0; L < 8; ++L) {
-    v5[L] = compensate<kTables.sqrt2>(at<kRows>(x, L, 3));
-    v6[L] = compensate<kTables.sqrt2>(at<kRows>(x, L, 5));
+    v5[L] = compensate<kTablesN<N>.sqrt2>(at<kRows>(x, L, 3));
+    v6[L] = compensate<kTablesN<N>.sqrt2>(at<kRows>(x, L, 5));
   }
   region();
   int e0[8], e1[8], a6[8], b6[8], a3[8], b3[8], a1[8], b1[8];
@@ -169,9 +170,9 @@ __device__ __forceinline__ void inverse_pass(int (&x)[64]) {
     a1[L] = v7 - v5[L];  // u5
     b1[L] = v4 - v6[L];  // u6: (t5, t6) = R(u5, u6; -pi/16)
   }
-  cordic_lines<-1>(a1, b1, a3, b3, a6, b6);
+  cordic_lines<N, -1>(a1, b1, a3, b3, a6, b6);
   region();
-  gains_lines(a1, b1, a3, b3, a6, b6);
+  gains_lines<N>(a1, b1, a3, b3, a6, b6);
   region();
 #pragma unroll
   for (int L = 0; L < 8; ++L) {

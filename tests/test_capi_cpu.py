@@ -125,19 +125,40 @@ def test_recipe_info_rejects_null(lib):
     assert lib.dct_recipe_tables(None, None) == codec.DCT_ERR_INVALID
 
 
-def test_quantizer_magic_lemma():
-    # The fused kernel divides m < 2^14 by Q as (m * ceil(2^k / Q)) >> k with
-    # k = 14 + ceil(log2 Q), using 24-bit multiplies.  Check that lemma for every
-    # table entry of every qs the library accepts (exhaustively over m).
-    m = np.arange(1 << 14, dtype=np.int64)
-    Qs = sorted({1 + (1 + s) * qs for qs in range(1, 1025) for s in range(15)})
-    for Q in Qs:
-        k = 14 + (Q - 1).bit_length()       # 2^(k-14) is the smallest power of two >= Q
-        magic = -(-(1 << k) // Q)
-        assert magic < (1 << 24)
-        prod = m * magic
-        assert prod.max() < (1 << 32)
-        assert np.array_equal(prod >> k, m // Q), Q
+RECIPES = [(10, 12, 12)] + sorted((n, F, G) for n in (4, 6, 8, 10, 12) for F, G in ((8, 8), (12, 12), (16, 12))
+                                   if (n, F, G) != (10, 12, 12))
+
+
+def test_recipe_family_is_built(lib):
+    got = codec.recipe_list()
+    assert got[0] == (10, 12, 12)
+    assert sorted(got) == sorted(RECIPES)
+    for r in RECIPES:
+        assert codec.recipe_supported(*r)
+    for r in ((10, 12, 8), (5, 12, 12), (10, 16, 16), (0, 0, 0)):
+        assert not codec.recipe_supported(*r)
+
+
+def test_recipe_family_constants_agree_with_oracle(lib, oracle_mod):
+    for n in sorted({r[0] for r in RECIPES}):
+        dirs, gains = codec.recipe_tables(n)
+        odirs, ogains = oracle_mod.recipe_tables_n(n)
+        assert np.array_equal(np.array(dirs), odirs), n
+        assert list(gains) == [int(g) for g in ogains], n
+    d = (C.c_int32 * 64)()
+    g = (C.c_int32 * 4)()
+    assert lib.dct_recipe_tables_n(7, d, g) == codec.DCT_ERR_UNSUPPORTED
+    assert lib.dct_recipe_tables_n(10, None, g) == codec.DCT_ERR_INVALID
+
+
+def test_codec_recipe_rejects(lib):
+    ok = (P8, 8, 8, 8, 10, 12, 12, 4, P8, 8, None, P8, None)
+    assert lib.dct_codec_recipe(*(ok[:4] + (5, 12, 12) + ok[7:])) == codec.DCT_ERR_UNSUPPORTED
+    assert lib.dct_codec_recipe(*(ok[:4] + (10, 16, 16) + ok[7:])) == codec.DCT_ERR_UNSUPPORTED
+    assert lib.dct_codec_recipe(*((None,) + ok[1:])) == codec.DCT_ERR_INVALID
+    assert lib.dct_codec_recipe(*(ok[:7] + (0,) + ok[8:])) == codec.DCT_ERR_INVALID
+    assert lib.dct_codec_recipe(*(ok[:11] + (None, None))) == codec.DCT_ERR_INVALID
+
 
 
 def test_bands_match_whole_image(oracle_mod):
