@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="no GPU work: condense the rocprofv3 outputs under DIR (subfolders trace, "
                          "fetch, write, copy_fetch, copy_write, sq) into the JSON given by --out")
-    ap.add_argument("--kernel", default="void dct::codec_kernel<false>",
+    ap.add_argument("--kernel", default="void dct::codec_kernel<dct::Recipe<10, 12, 12>, false>",
                     help="kernel-name prefix for --summarize-profile")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "codec_kernel_8192.json"))
     return ap.parse_args()
