@@ -53,6 +53,13 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 64 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--workload", choices=("codec", "precision", "pareto"), default="codec",
+                    help="codec (default): the fused integer codec at 8192x8192; precision: "
+                         "YCbCr + floating-point forms over 256 RGB 2048x2048 images; pareto: "
+                         "every built recipe R(n, F, G) at 8192x8192 (one JSON line each)")
+    ap.add_argument("--images", type=int, default=256, help="precision workload: images per batch")
+    ap.add_argument("--distinct", type=int, default=8,
+                    help="precision workload: distinct synthetic images, repeated to fill the batch")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="no GPU work: condense the rocprofv3 outputs under DIR (subfolders trace, "
                          "fetch, write, copy_fetch, copy_write, sq) into the JSON given by --out")
@@ -153,6 +160,174 @@ def cpu_baseline(imgs, qs):
                       f"over block-row bands: {dt:.2f} s wall, {cpu:.1f} s CPU"}, first[0], first[1]
 
 
+PREC_SIZE = 2048
+PREC_QS = 8
+FORM_NAMES = ("f32", "f16", "bf16")
+
+
+def bench_precision(args):
+    """The precision form: a batch of RGB 2048x2048 images, converted to YCbCr and
+    each plane coded with a floating-point transform.  The batch is stacked
+    vertically into one 2048-wide plane per channel (2048 is a multiple of 8, so no
+    block spans two images), one YCbCr launch and three codec launches per step."""
+    import numpy as np
+    import torch
+
+    from paper_1306_1373_amd import codec
+    from paper_1306_1373_amd.synth import synth_rgb
+
+    codec.load()
+    dev = torch.device("cuda:0")
+    S, N, D = PREC_SIZE, args.images, max(1, min(args.distinct, args.images))
+    print(f"[bench] generating {D} synthetic RGB {S}x{S} images for a batch of {N}", file=sys.stderr, flush=True)
+    host = [synth_rgb(S, S, 100 + i) for i in range(D)]
+    rgb = torch.empty((N * S, S, 3), dtype=torch.uint8, device=dev)
+    for i in range(N):
+        rgb[i * S:(i + 1) * S].copy_(torch.from_numpy(host[i % D]).to(dev))
+    planes = tuple(codec.new_plane(S, N * S, dev) for _ in range(3))
+    outs = tuple(codec.new_plane(S, N * S, dev) for _ in range(3))
+    sse = torch.zeros(3, dtype=torch.int64, device=dev)
+    px = 3 * N * S * S
+    torch.cuda.synchronize()
+
+    # accuracy against the FP64 oracle on the first image's three planes
+    from oracle import bands
+    import oracle as orc
+    ycc = orc.rgb_to_ycbcr(host[0])
+    codec.dct_rgb_to_ycbcr(rgb, planes)
+    dev_ycc = [p[:S].cpu().numpy() for p in planes]
+    ycc_exact = all(np.array_equal(a, b) for a, b in zip(ycc, dev_ycc))
+    cores = len(os.sched_getaffinity(0))
+    ref_psnr, ref_coef = [], []
+    for pl in ycc:
+        rec = bands.exact_codec_bands(pl, PREC_QS, threads=cores)
+        ref_psnr.append(orc.psnr(pl, rec))
+        ref_coef.append(orc.exact_forward(pl))
+
+    for form in FORM_NAMES:
+        errs, dpsnr = [], []
+        for c in range(3):
+            coef = codec.dct_forward_float(planes[c][:S], form).cpu().numpy()
+            errs.append(float(np.abs(coef - ref_coef[c]).max()))
+            _, s1 = codec.dct_codec_float(planes[c][:S], form, PREC_QS, dst=outs[c][:S], sse=sse[c:c + 1])
+            dpsnr.append(codec.psnr_from_sse(int(s1.cpu()[0]), S, S) - ref_psnr[c])
+
+        def step():
+            codec.dct_rgb_to_ycbcr(rgb, planes)
+            for c in range(3):
+                codec.dct_codec_float(planes[c], form, PREC_QS, dst=outs[c], sse=sse[c:c + 1])
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            step()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        # the codec launches alone (fill + transform kernel), for the kernel's roofline
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record()
+        for _ in range(args.steps):
+            for c in range(3):
+                codec.dct_codec_float(planes[c], form, PREC_QS, dst=outs[c], sse=sse[c:c + 1])
+        k1.record()
+        torch.cuda.synchronize()
+        kms = k0.elapsed_time(k1) / args.steps / 3
+        plane_px = N * S * S
+        hbm = 2.0 * plane_px / (kms * 1e-3) / 1e9
+        flops = (256.0 if form != "f32" else 0.0) * plane_px / (kms * 1e-3) / 1e12
+        out = {
+            "metric": "Gpixel/s YCbCr + DCT+quant+IDCT per channel-pixel, floating-point form",
+            "value": round(px / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"f32": "f32", "f16": "f16 in, f32 accumulate", "bf16": "bf16 in, f32 accumulate"}[form],
+            "data": "synthetic",
+            "config": {"workload": f"{N} RGB {S}x{S} synthetic images ({D} distinct, repeated), integer "
+                                   f"YCbCr, each plane coded with the {form} form at qs={PREC_QS}",
+                       "images": N, "size": S, "qs": PREC_QS, "form": form},
+            "accuracy": {"max_abs_coef_err": [round(e, 6) for e in errs],
+                         "psnr_delta_db": [round(d, 5) for d in dpsnr], "planes": "Y Cb Cr of image 0",
+                         "reference": "FP64 exact DCT codec (oracle)", "ycbcr_bit_exact": ycc_exact},
+            "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(hbm / HBM_PEAK_GBPS, 4), "traffic": None,
+                         "kernel": "kron_kernel" if form != "f32" else "loeffler_f32_kernel",
+                         "avg_kernel_ms": round(kms, 4), "bytes_per_pixel": 2.0,
+                         "mfma_tflops": round(flops, 1) if form != "f32" else None},
+        }
+        print(json.dumps(out), flush=True)
+
+
+def ops_per_pixel(n):
+    """Algorithmic integer operations per pixel of recipe R(n, F, G), counted as for
+    the default recipe (only the micro-rotation count changes the total)."""
+    per_1d = 8 + 6 + 6 + 3 * (4 * n - 2) + 8 * 3
+    return (32 * per_1d + 64 * (2 + 4 + 4 + 5 + 3)) / 64.0
+
+
+def bench_pareto(args):
+    """Every built recipe R(n, F, G) on the 8192x8192 rotation: Gpixel/s against
+    PSNR, each checked bit for bit against the oracle's recipe mode on image 0."""
+    import numpy as np
+    import torch
+
+    from oracle import bands
+    from paper_1306_1373_amd import codec
+    from paper_1306_1373_amd.synth import sigma_for_seed, synth_image
+
+    codec.load()
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {N_IMAGES} synthetic {W}x{H} images", file=sys.stderr, flush=True)
+    host_imgs = [synth_image(W, H, s, sigma_for_seed(s)) for s in range(N_IMAGES)]
+    srcs, dsts = [], []
+    for img in host_imgs:
+        p = codec.new_plane(W, H, dev)
+        p.copy_(torch.from_numpy(img).to(dev))
+        srcs.append(p)
+        dsts.append(codec.new_plane(W, H, dev))
+    cores = len(os.sched_getaffinity(0))
+    exact = None
+    for recipe in codec.recipe_list():
+        total = args.warmup + args.steps
+        sse = torch.zeros(total, dtype=torch.int64, device=dev)
+
+        def step(k):
+            i = k % N_IMAGES
+            codec.dct_codec_recipe(srcs[i], recipe, QS, dst=dsts[i], sse=sse[k:k + 1])
+
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for k in range(args.warmup, total):
+            step(k)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        gpx = W * H / (ms * 1e-3) / 1e9
+        sse0 = int(sse[0].cpu())
+        orec, osse = bands.codec_bands(host_imgs[0], QS, threads=cores, recipe=recipe)
+        parity = bool(osse == sse0 and np.array_equal(dsts[0].cpu().numpy(), orec))
+        ops = ops_per_pixel(recipe[0])
+        print(json.dumps({
+            "metric": METRIC, "value": round(gpx, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"{W}x{H} uint8 grayscale synthetic images (seeds 0-4), fused codec, "
+                                   f"recipe n={recipe[0]} F={recipe[1]} G={recipe[2]} P=15, qs={QS}",
+                       "recipe": list(recipe), "qs": QS, "entry_point": "dct_codec_recipe"},
+            "psnr_db_seed0": round(codec.psnr_from_sse(sse0, W, H), 6), "parity": parity,
+            "roofline": {"bound": "alu", "achieved": round(ops * gpx / 1000.0, 3),
+                         "peak": round(INT32_PEAK_TOPS, 2), "unit": "Tops/s",
+                         "frac": round(ops * gpx / 1000.0 / INT32_PEAK_TOPS, 4), "traffic": None,
+                         "ops_per_pixel": ops},
+        }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -165,6 +340,12 @@ def main():
         return
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.kernel, args.out)
+        return
+    if args.workload == "precision":
+        bench_precision(args)
+        return
+    if args.workload == "pareto":
+        bench_pareto(args)
         return
     import numpy as np
     import torch

@@ -43,7 +43,10 @@
  *     and owns every buffer; the library never frees caller memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
  *     enqueue their kernels on it and return without waiting unless stated.
- *   - Sizes: 1 <= W, H <= 65535; 1 <= qs <= 1024.
+ *   - Sizes: 1 <= W <= 65535, 1 <= H <= 2^24 (within the 2^32 rule above);
+ *     1 <= qs <= 1024.  Blocks never span two images stacked vertically in one
+ *     plane when each image's height is a multiple of 8, so such a stack codes
+ *     exactly like its images one by one.
  *   - Every call returns a dct_status.  Arguments are checked before anything is
  *     enqueued (DCT_ERR_INVALID); a failed launch gives DCT_ERR_DEVICE.  The
  *     library never aborts and never throws across this interface.

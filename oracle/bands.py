@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
-from . import cordic_codec, cordic_forward, cordic_inverse, exact_codec, grid
+from . import cordic_codec, cordic_forward, cordic_inverse, exact_codec, grid, recipe_codec
 
 
 def _bands(H: int, nbands: int):
@@ -24,8 +24,9 @@ def _bands(H: int, nbands: int):
     return out
 
 
-def codec_bands(img: np.ndarray, qs: int, threads: int = 8, want_q: bool = False):
-    """(reconstruction, sse[, qcoef]) of the recipe codec, band-parallel."""
+def codec_bands(img: np.ndarray, qs: int, threads: int = 8, want_q: bool = False, recipe=None):
+    """(reconstruction, sse[, qcoef]) of the recipe codec (the default recipe, or
+    recipe = (n, F, G)), band-parallel."""
     H, W = img.shape
     bw, _ = grid(W, H)
     rec = np.empty((H, W), np.uint8)
@@ -34,7 +35,8 @@ def codec_bands(img: np.ndarray, qs: int, threads: int = 8, want_q: bool = False
     def run(b):
         y0, y1, r0, r1 = b
         band = np.ascontiguousarray(img[y0:y1])
-        out = cordic_codec(band, qs, want_q=want_q)
+        out = cordic_codec(band, qs, want_q=want_q) if recipe is None else \
+            recipe_codec(*recipe, band, qs, want_q=want_q)
         rec[y0:y1] = out[0]
         if want_q:
             q[r0 * bw:r1 * bw] = out[2]

@@ -17,7 +17,8 @@
 namespace {
 
 constexpr int kMaxDevices = 64;
-constexpr int kMaxDim = 65535;
+constexpr int kMaxW = 65535;
+constexpr int kMaxH = 1 << 24;  // a stack of images coded as one plane; the 2^32 offset rule binds first
 constexpr int kMaxQs = 1024;
 
 std::mutex g_lock;                                   // guards the scratch table and dct_psnr
@@ -28,7 +29,7 @@ bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 
 // The kernels address a plane with 32-bit offsets: (H - 1) stride + W < 2^32.
 bool plane_ok(const void *p, int32_t W, int32_t H, int32_t stride) {
-  return p != nullptr && aligned(p, 8) && W >= 1 && W <= kMaxDim && H >= 1 && H <= kMaxDim &&
+  return p != nullptr && aligned(p, 8) && W >= 1 && W <= kMaxW && H >= 1 && H <= kMaxH &&
          stride >= W && stride % 8 == 0 &&
          static_cast<uint64_t>(H - 1) * static_cast<uint64_t>(stride) + static_cast<uint64_t>(W) <
              (uint64_t{1} << 32);
@@ -327,15 +328,17 @@ int dct_codec_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride
 
 int dct_rgb_to_ycbcr(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, uint8_t *y, uint8_t *cb,
                      uint8_t *cr, int32_t plane_stride, void *stream) {
-  if (rgb == nullptr || W < 1 || W > kMaxDim || H < 1 || H > kMaxDim || rgb_stride < 3 * W ||
+  if (rgb == nullptr || W < 1 || W > kMaxW || H < 1 || H > kMaxH || rgb_stride < 3 * W ||
       static_cast<uint64_t>(H - 1) * static_cast<uint64_t>(rgb_stride) + 3u * static_cast<uint64_t>(W) >=
           (uint64_t{1} << 32) ||
       !plane_ok(y, W, H, plane_stride) || !plane_ok(cb, W, H, plane_stride) || !plane_ok(cr, W, H, plane_stride))
     return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
-  const int64_t total = static_cast<int64_t>(W) * H;
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(total), 8192));
-  dct::ycbcr_kernel<<<grid, dct::kWg, 0, as_stream(stream)>>>(rgb, W, H, rgb_stride, y, cb, cr, plane_stride);
+  const int64_t total = static_cast<int64_t>((W + 7) / 8) * H;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(total), 16384));
+  const bool vec_ok = aligned(rgb, 8) && rgb_stride % 8 == 0;
+  dct::ycbcr_kernel<<<grid, dct::kWg, 0, as_stream(stream)>>>(rgb, W, H, rgb_stride, y, cb, cr, plane_stride,
+                                                              vec_ok);
   return launched();
 }
 

@@ -273,31 +273,92 @@ struct MfmaTraits<true> {
 
 inline constexpr int kMfmaWaves = 4;  // waves per workgroup; each wave codes 16 blocks per step
 
-// One 8-byte row of block (by, bx), row r of the block, clamped at the edges.
-__device__ __forceinline__ uint2 load_row(const uint8_t *__restrict__ src, int W, int H, int stride, int by, int bx,
-                                          int r, bool full) {
-  const int x0 = bx * 8;
+// Register-only layout of the matrix form.  With blocks as the N dimension,
+// the forward product is F^T = K X^T (M = coefficient, K = pixel) and the
+// inverse X^T = K^T F^T (M = pixel, K = coefficient).  The inner dimension of a
+// product may be taken in any order, so both use the order
+//     sigma(s, g, e) = 16 (2 s + e / 4) + 4 g + e % 4
+// for K-step s, lane group g = lane / 16 and element e of the 8-element operand.
+// Then, for lane (i = lane % 16, g):
+//   * the forward B operand is pixels sigma(s, g, 0..7) of block i: the four
+//     4-byte words w[t] = row 2t + g/2, columns 4(g%2)..4(g%2)+3 (t = 0..3),
+//     loaded straight from the plane;
+//   * the forward result D[4g + r] of M-tile t is coefficient 16t + 4g + r of
+//     block i, which is element e = 4(t % 2) + r of the inverse B operand of
+//     K-step s = t / 2, so the quantized values never leave the lane;
+//   * the inverse result D[4g + r] of M-tile t is pixel 16t + 4g + r of block
+//     i, byte r of the lane's own word w[t], so it is stored where it was
+//     loaded and the SSE needs no second read.
+// No LDS and no barrier is involved.  The A operands are the constant matrix
+// K[j][k] (coefficient j, pixel k) in that order, held in registers.
+__device__ __forceinline__ int sigma_index(int s, int g, int e) { return 16 * (2 * s + (e >> 2)) + 4 * g + (e & 3); }
+
+// the four words of lane group g of a block: row 2t + g/2, bytes 4(g%2)..+3
+__device__ __forceinline__ void load_words(const uint8_t *__restrict__ src, int W, int H, int stride, int by,
+                                           int bx, int g, bool full, uint32_t (&w)[4]) {
+  const int x0 = bx * 8 + 4 * (g & 1), y0 = by * 8 + (g >> 1);
   if (full) {
-    const uint32_t off = static_cast<uint32_t>(by * 8 + r) * static_cast<uint32_t>(stride) + static_cast<uint32_t>(x0);
-    return *reinterpret_cast<const uint2 *>(src + off);
-  }
-  const uint8_t *row = src + static_cast<size_t>(min(by * 8 + r, H - 1)) * stride;
-  uint32_t lo = 0, hi = 0;
+    const uint32_t off = static_cast<uint32_t>(y0) * static_cast<uint32_t>(stride) + static_cast<uint32_t>(x0);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    lo |= static_cast<uint32_t>(row[min(x0 + j, W - 1)]) << (8 * j);
-    hi |= static_cast<uint32_t>(row[min(x0 + 4 + j, W - 1)]) << (8 * j);
+    for (int t = 0; t < 4; ++t)
+      w[t] = *reinterpret_cast<const uint32_t *>(src + (off + static_cast<uint32_t>(2 * t * stride)));
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint8_t *row = src + static_cast<size_t>(min(y0 + 2 * t, H - 1)) * stride;
+      uint32_t v = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v |= static_cast<uint32_t>(row[min(x0 + r, W - 1)]) << (8 * r);
+      w[t] = v;
+    }
   }
-  return make_uint2(lo, hi);
 }
 
-// Lane layouts of v_mfma_f32_16x16x32 (lane l, i = l % 16, g = l / 16):
-//   A[i][8g + e], B[8g + e][i], D[4g + r][i]  (e = 0..7, r = 0..3).
-// Forward, K-step s, N-tile t:  A = pixels of block i, row 4s + g;
-//   B[k][j] = K[j][k] for k = 32s + 8g + e, j = 16t + i.
-// D[4g + r][16t + i] = F of block 4g + r, coefficient 16t + i.
-// Inverse: A[i][j = 32s + 8g + e] = dequantized F of block i; B[j][k] = K[j][k]
-// for k = 16t + i; D[4g + r][16t + i] = pixel 16t + i of block 4g + r.
+__device__ __forceinline__ void store_words(uint8_t *__restrict__ dst, int W, int H, int stride, int by, int bx,
+                                            int g, bool full, const uint32_t (&w)[4]) {
+  const int x0 = bx * 8 + 4 * (g & 1), y0 = by * 8 + (g >> 1);
+  if (full) {
+    const uint32_t off = static_cast<uint32_t>(y0) * static_cast<uint32_t>(stride) + static_cast<uint32_t>(x0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      *reinterpret_cast<uint32_t *>(dst + (off + static_cast<uint32_t>(2 * t * stride))) = w[t];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int y = y0 + 2 * t;
+      if (y < H) {
+        uint8_t *row = dst + static_cast<size_t>(y) * stride;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (x0 + r < W) row[x0 + r] = static_cast<uint8_t>(w[t] >> (8 * r));
+      }
+    }
+  }
+}
+
+// SSE of the lane's four words; edge blocks count only pixels inside W x H
+__device__ __forceinline__ uint32_t words_sse(const uint32_t (&a)[4], const uint32_t (&b)[4], int W, int H, int by,
+                                              int bx, int g, bool full) {
+  uint32_t mask = 0xffffffffu;
+  int rows = 8;
+  if (!full) {
+    const int cols = min(max(W - (bx * 8 + 4 * (g & 1)), 0), 4);
+    mask = cols >= 4 ? 0xffffffffu : (1u << (8 * cols)) - 1u;
+    rows = H - by * 8 - (g >> 1);
+  }
+  uint32_t pp = 0, pr = 0, rr = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const bool in = full || 2 * t < rows;
+    const uint32_t x = in ? a[t] & mask : 0u, y = in ? b[t] & mask : 0u;
+    pp = __builtin_amdgcn_udot4(x, x, pp, false);
+    pr = __builtin_amdgcn_udot4(x, y, pr, false);
+    rr = __builtin_amdgcn_udot4(y, y, rr, false);
+  }
+  return pp - 2u * pr + rr;
+}
+
+// kCodec = false: FP32 coefficients only; true: quantize, inverse, reconstruct, SSE.
 template <bool kBf16, bool kCodec>
 __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__restrict__ src, int W, int H,
                                                               int stride, int bw, int nblocks, int ntiles,
@@ -307,122 +368,100 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
   using T = MfmaTraits<kBf16>;
   typedef typename T::vec vec;
   typedef typename T::elem elem;
-  __shared__ uint16_t lds_coef[kMfmaWaves][16 * 64];
-  __shared__ uint8_t lds_pix[kMfmaWaves][16 * 64];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
   const uint16_t *K = T::table();
 
-  // constant B operands (each lane: 2 K-steps x 4 N-tiles x 8 elements, per direction)
-  vec bf[2][4], bi[2][4];
+  // constant A operands: forward fa[t][s] = K[16t + i][sigma(s, g, e)],
+  // inverse ia[t][s] = K[sigma(s, g, e)][16t + i]
+  vec fa[4][2], ia[4][2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        bf[s][t][e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + 32 * s + 8 * g + e]);
-        bi[s][t][e] = __builtin_bit_cast(elem, K[(32 * s + 8 * g + e) * 64 + 16 * t + i]);
-      }
-
-  uint64_t err = 0;
-  // workgroup-uniform loop over groups of kMfmaWaves tiles of 16 blocks
-  for (int base = blockIdx.x * kMfmaWaves; base < ntiles; base += gridDim.x * kMfmaWaves) {
-    const int tile = base + wave;
-    // a1: this lane's block i of the tile: rows g and 4 + g
-    const int b = tile * 16 + i;
-    const BlockPos p = block_pos(b, W, H, bw, nblocks);
-    uint2 raw[2] = {make_uint2(0, 0), make_uint2(0, 0)};
-    if (p.live) {
-      raw[0] = load_row(src, W, H, stride, p.by, p.bx, g, p.full);
-      raw[1] = load_row(src, W, H, stride, p.by, p.bx, 4 + g, p.full);
-    }
-    vec a[2];
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const uint32_t w = e < 4 ? raw[s].x : raw[s].y;
-        a[s][e] = static_cast<elem>(static_cast<float>(static_cast<int>((w >> (8 * (e & 3))) & 0xffu) - 128));
+        fa[t][s][e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
+        if constexpr (kCodec) ia[t][s][e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
       }
-    // forward product
+  // the table entry of each coefficient this lane holds: 16t + 4g + r, u + v = 2t + r + g/2 + 4(g%2)
+  float qv[4][4], rq[4][4];
+  if constexpr (kCodec) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int sidx = 2 * t + r + (g >> 1) + 4 * (g & 1);
+        float qq = fq.Q[0], rr = fq.rcp[0];
+#pragma unroll
+        for (int k = 1; k < 15; ++k) {
+          qq = sidx == k ? fq.Q[k] : qq;
+          rr = sidx == k ? fq.rcp[k] : rr;
+        }
+        qv[t][r] = qq;
+        rq[t][r] = rr;
+      }
+  }
+
+  uint64_t err = 0;
+  // each wave walks its tiles with the next tile's words already in flight
+  const int step = gridDim.x * kMfmaWaves;
+  int tile = blockIdx.x * kMfmaWaves + wave;
+  BlockPos p = block_pos(tile * 16 + i, W, H, bw, nblocks);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if (tile < ntiles && p.live) load_words(src, W, H, stride, p.by, p.bx, g, p.full, w);
+  for (; tile < ntiles; tile += step) {
+    const int b = tile * 16 + i;
+    const BlockPos pn = block_pos(b + 16 * step, W, H, bw, nblocks);
+    uint32_t wn[4] = {0u, 0u, 0u, 0u};
+    if (tile + step < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, wn);
+    // forward B operand: pixels sigma(s, g, e) - 128
+    vec bx[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t word = w[2 * s + (e >> 2)];
+        bx[s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
+      }
     f32x4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < 2; ++s) acc[t] = T::mma(a[s], bf[s][t], acc[t]);
+      acc[t] = T::mma(fa[t][0], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
+      acc[t] = T::mma(fa[t][1], bx[1], acc[t]);
     }
     if constexpr (!kCodec) {
+      if (p.live) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int bo = tile * 16 + 4 * g + r;
-        if (bo < nblocks) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) coef[static_cast<size_t>(bo) * 64 + 16 * t + i] = acc[t][r];
-        }
+        for (int t = 0; t < 4; ++t)
+          *reinterpret_cast<float4 *>(coef + static_cast<size_t>(b) * 64 + 16 * t + 4 * g) =
+              make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
       }
     } else {
-      // quantize, dequantize, and lay the block's values out for the inverse
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = 16 * t + i, sidx = (j >> 3) + (j & 7);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float d = fquant(acc[t][r], fq.Q[sidx], fq.rcp[sidx]);
-          lds_coef[wave][(4 * g + r) * 64 + j] = __builtin_bit_cast(uint16_t, static_cast<elem>(d));
-        }
-      }
-      __syncthreads();
-      vec ai[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          ai[s][e] = __builtin_bit_cast(elem, lds_coef[wave][i * 64 + 32 * s + 8 * g + e]);
-      f32x4 rx[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        rx[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 2; ++s) rx[t] = T::mma(ai[s], bi[s][t], rx[t]);
-      }
+      // quantize and dequantize in place: element e = 4(t % 2) + r of inverse step t / 2
+      vec bq[2];
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          lds_pix[wave][(4 * g + r) * 64 + 16 * t + i] = static_cast<uint8_t>(freconstruct(rx[t][r]));
-      __syncthreads();
-      // rows g and 4 + g of block i back to the lane that loaded them
-      uint32_t rec[16] = {}, pix[16] = {};
+          bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], qv[t][r], rq[t][r]));
+      uint32_t rec[4];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int r = 4 * s + g;
-        const uint2 w = *reinterpret_cast<const uint2 *>(&lds_pix[wave][i * 64 + 8 * r]);
-        rec[2 * r] = w.x;
-        rec[2 * r + 1] = w.y;
-        pix[2 * r] = raw[s].x;
-        pix[2 * r + 1] = raw[s].y;
+      for (int t = 0; t < 4; ++t) {
+        f32x4 x = T::mma(ia[t][0], bq[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        x = T::mma(ia[t][1], bq[1], x);
+        uint32_t v = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v |= freconstruct(x[r]) << (8 * r);
+        rec[t] = v;
       }
       if (p.live) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int r = 4 * s + g, y = p.by * 8 + r;
-          if (p.full) {
-            const uint32_t off = static_cast<uint32_t>(y) * static_cast<uint32_t>(dst_stride) +
-                                 static_cast<uint32_t>(p.bx * 8);
-            *reinterpret_cast<uint2 *>(dst + off) = make_uint2(rec[2 * r], rec[2 * r + 1]);
-          } else if (y < H) {
-            uint8_t *row = dst + static_cast<size_t>(y) * dst_stride;
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj)
-              if (p.bx * 8 + jj < W) row[p.bx * 8 + jj] = static_cast<uint8_t>(rec[2 * r + (jj >> 2)] >> (8 * (jj & 3)));
-          }
-        }
-        // SSE of the two rows this lane holds (the other rows are zero in both)
-        err += block_sse(pix, rec, W, H, p.by, p.bx, p.full);
+        store_words(dst, W, H, dst_stride, p.by, p.bx, g, p.full, rec);
+        err += words_sse(w, rec, W, H, p.by, p.bx, g, p.full);
       }
-      __syncthreads();
     }
+    p = pn;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = wn[k];
   }
   if constexpr (kCodec) workgroup_add<64 * kMfmaWaves>(err, sse);
 }
@@ -435,22 +474,57 @@ namespace dct {
 //   Y  = (19595 R + 38470 G + 7471 B + 2^15) >> 16
 //   Cb = ((-11058 R - 21710 G + 32768 B + 2^15) >> 16) + 128
 //   Cr = ((32768 R - 27439 G - 5329 B + 2^15) >> 16) + 128, each clamped to [0, 255].
+__device__ __forceinline__ uint32_t ycc_byte(int v) { return static_cast<uint32_t>(min(max(v, 0), 255)); }
+
+// One pixel: (Y, Cb, Cr) as three bytes.
+__device__ __forceinline__ void ycc(int R, int G, int B, uint32_t &y, uint32_t &cb, uint32_t &cr) {
+  y = ycc_byte((19595 * R + 38470 * G + 7471 * B + (1 << 15)) >> 16);
+  cb = ycc_byte(((-11058 * R - 21710 * G + 32768 * B + (1 << 15)) >> 16) + 128);
+  cr = ycc_byte(((32768 * R - 27439 * G - 5329 * B + (1 << 15)) >> 16) + 128);
+}
+
+// One thread per group of 8 pixels of a row, grid-stride.  A group inside the
+// row of an 8-byte-aligned RGB row (rgb_stride % 8 == 0 and base aligned) reads
+// three 8-byte words and writes one 8-byte word per plane; other groups go byte
+// by byte.
 __global__ __launch_bounds__(kWg) void ycbcr_kernel(const uint8_t *__restrict__ rgb, int W, int H, int rgb_stride,
                                                     uint8_t *__restrict__ y, uint8_t *__restrict__ cb,
-                                                    uint8_t *__restrict__ cr, int plane_stride) {
-  const int64_t total = static_cast<int64_t>(W) * H;
+                                                    uint8_t *__restrict__ cr, int plane_stride, bool vec_ok) {
+  const int groups = (W + 7) / 8;
+  const int64_t total = static_cast<int64_t>(groups) * H;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * kWg + threadIdx.x; t < total;
        t += static_cast<int64_t>(gridDim.x) * kWg) {
-    const int row = static_cast<int>(t / W), col = static_cast<int>(t - static_cast<int64_t>(row) * W);
-    const uint8_t *px = rgb + static_cast<size_t>(row) * rgb_stride + 3 * col;
-    const int R = px[0], G = px[1], B = px[2];
-    const int yy = (19595 * R + 38470 * G + 7471 * B + (1 << 15)) >> 16;
-    const int bb = ((-11058 * R - 21710 * G + 32768 * B + (1 << 15)) >> 16) + 128;
-    const int rr = ((32768 * R - 27439 * G - 5329 * B + (1 << 15)) >> 16) + 128;
-    const size_t o = static_cast<size_t>(row) * plane_stride + col;
-    y[o] = static_cast<uint8_t>(min(max(yy, 0), 255));
-    cb[o] = static_cast<uint8_t>(min(max(bb, 0), 255));
-    cr[o] = static_cast<uint8_t>(min(max(rr, 0), 255));
+    const int row = static_cast<int>(t / groups), x0 = static_cast<int>(t - static_cast<int64_t>(row) * groups) * 8;
+    const uint8_t *px = rgb + static_cast<size_t>(row) * rgb_stride + 3 * x0;
+    const size_t o = static_cast<size_t>(row) * plane_stride + x0;
+    if (vec_ok && x0 + 8 <= W) {
+      const uint2 a = reinterpret_cast<const uint2 *>(px)[0], b2 = reinterpret_cast<const uint2 *>(px)[1],
+                  c = reinterpret_cast<const uint2 *>(px)[2];
+      const uint32_t wv[6] = {a.x, a.y, b2.x, b2.y, c.x, c.y};
+      uint32_t yy[2] = {0u, 0u}, bb[2] = {0u, 0u}, rr[2] = {0u, 0u};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int R = (wv[(3 * k) >> 2] >> (8 * ((3 * k) & 3))) & 0xff;
+        const int G = (wv[(3 * k + 1) >> 2] >> (8 * ((3 * k + 1) & 3))) & 0xff;
+        const int B = (wv[(3 * k + 2) >> 2] >> (8 * ((3 * k + 2) & 3))) & 0xff;
+        uint32_t vy, vb, vr;
+        ycc(R, G, B, vy, vb, vr);
+        yy[k >> 2] |= vy << (8 * (k & 3));
+        bb[k >> 2] |= vb << (8 * (k & 3));
+        rr[k >> 2] |= vr << (8 * (k & 3));
+      }
+      *reinterpret_cast<uint2 *>(y + o) = make_uint2(yy[0], yy[1]);
+      *reinterpret_cast<uint2 *>(cb + o) = make_uint2(bb[0], bb[1]);
+      *reinterpret_cast<uint2 *>(cr + o) = make_uint2(rr[0], rr[1]);
+    } else {
+      for (int k = 0; k < 8 && x0 + k < W; ++k) {
+        uint32_t vy, vb, vr;
+        ycc(px[3 * k], px[3 * k + 1], px[3 * k + 2], vy, vb, vr);
+        y[o + k] = static_cast<uint8_t>(vy);
+        cb[o + k] = static_cast<uint8_t>(vb);
+        cr[o + k] = static_cast<uint8_t>(vr);
+      }
+    }
   }
 }
 

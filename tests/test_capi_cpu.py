@@ -68,6 +68,7 @@ MIS = C.c_void_p(4100)    # 4-byte aligned only
     (P8, 16, 8, 8, P16),            # stride < W
     (MIS, 8, 8, 8, P16),            # misaligned source
     (P8, 65535, 65535, 65544, P16),  # plane beyond 32-bit offsets
+    (P8, 8, (1 << 24) + 8, 8, P16),  # H beyond 2^24
     (P8, 8, 8, 8, None),            # null coefficients
     (P8, 8, 8, 8, C.c_void_p(4104)),  # misaligned coefficients
 ])

@@ -181,10 +181,19 @@ def test_codec_tie_aware_pixels(hip, oracle_mod, form, W, H, qs):
 def test_ycbcr_bit_exact(hip, oracle_mod):
     import torch
     rng = np.random.default_rng(52)
-    rgb = rng.integers(0, 256, (97, 131, 3), dtype=np.uint8)
-    planes = hip.dct_rgb_to_ycbcr(torch.from_numpy(rgb).cuda())
-    for got, ref in zip(planes, oracle_mod.rgb_to_ycbcr(rgb)):
-        assert np.array_equal(got.cpu().numpy(), ref)
+    # packed rows of odd width (byte path), packed rows of width 256 (8-pixel path),
+    # and rows padded to an 8-byte multiple with a ragged tail (both paths)
+    for (H, W, pitch) in ((97, 131, None), (50, 256, None), (41, 131, 408), (3, 8, 24), (1, 1, None)):
+        rgb = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+        if pitch is None:
+            dev = torch.from_numpy(rgb).cuda()
+        else:
+            buf = torch.zeros((H, pitch), dtype=torch.uint8, device="cuda")
+            buf[:, :3 * W] = torch.from_numpy(rgb.reshape(H, 3 * W)).cuda()
+            dev = buf.as_strided((H, W, 3), (pitch, 3, 1))
+        planes = hip.dct_rgb_to_ycbcr(dev)
+        for got, ref in zip(planes, oracle_mod.rgb_to_ycbcr(rgb)):
+            assert np.array_equal(got.cpu().numpy(), ref), (H, W, pitch)
 
 
 def test_precision_workload_image(hip, oracle_mod):
