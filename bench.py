@@ -53,11 +53,12 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 64 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=("codec", "precision", "pareto"), default="codec",
+    ap.add_argument("--workload", choices=("codec", "precision", "pareto", "batch"), default="codec",
                     help="codec (default): the fused integer codec at 8192x8192; precision: "
                          "YCbCr + floating-point forms over 256 RGB 2048x2048 images; pareto: "
                          "every built recipe R(n, F, G) at 8192x8192 (one JSON line each)")
     ap.add_argument("--images", type=int, default=256, help="precision workload: images per batch")
+    ap.add_argument("--batch-images", type=int, default=10000, help="batch workload: number of images")
     ap.add_argument("--distinct", type=int, default=8,
                     help="precision workload: distinct synthetic images, repeated to fill the batch")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -328,6 +329,115 @@ def bench_pareto(args):
         }), flush=True)
 
 
+def bench_batch(args):
+    """The batching form: images with W, H drawn uniformly from 64..4096 and qs from
+    {2, 4, 8, 16}, generated on the device, coded by one graph-captured launch
+    (launch shape from the tuner) and, for comparison, by one dct_codec call per
+    image.  A seeded sample of images is checked bit for bit against the oracle."""
+    import numpy as np
+    import torch
+
+    from oracle import bands
+    from paper_1306_1373_amd import codec
+    from paper_1306_1373_amd.autotune import tune_batch
+    from paper_1306_1373_amd.synth import synth_image_device
+
+    codec.load()
+    dev = torch.device("cuda:0")
+    n = args.batch_images
+    rng = np.random.default_rng(2024)
+    Ws = rng.integers(64, 4097, n)
+    Hs = rng.integers(64, 4097, n)
+    qss = rng.choice([2, 4, 8, 16], n)
+    pitches = ((Ws + 7) // 8) * 8
+    sizes = pitches * Hs
+    offs = np.concatenate([[0], np.cumsum((sizes + 255) // 256 * 256)])
+    total_px = int((Ws * Hs).sum())
+    print(f"[bench] {n} images, {total_px / 1e9:.2f} Gpixel, {offs[-1] / 2**30:.1f} GiB per buffer; "
+          f"generating on the device", file=sys.stderr, flush=True)
+    src_buf = torch.empty(int(offs[-1]), dtype=torch.uint8, device=dev)
+    dst_buf = torch.empty(int(offs[-1]), dtype=torch.uint8, device=dev)
+
+    def view(buf, k):
+        return buf[int(offs[k]):int(offs[k]) + int(sizes[k])].view(int(Hs[k]), int(pitches[k]))[:, :int(Ws[k])]
+
+    srcs = [view(src_buf, k) for k in range(n)]
+    dsts = [view(dst_buf, k) for k in range(n)]
+    for k in range(n):
+        synth_image_device(int(Ws[k]), int(Hs[k]), 20000 + k, 5.0, srcs[k])
+    torch.cuda.synchronize()
+    qs_list = [int(q) for q in qss]
+
+    print("[bench] tuning the launch shape", file=sys.stderr, flush=True)
+    tune, batch = tune_batch(srcs, dsts, qs_list, grids=(0, 2048, 4096, 8192), reps=2)
+    sse = torch.zeros(n, dtype=torch.int64, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        batch.run(tune.grid, sse=sse)             # warm on the capture stream
+        with torch.cuda.graph(graph, stream=side):
+            batch.run(tune.grid, sse=sse)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    sse_batch = sse.cpu().numpy().copy()
+
+    # the same images, one dct_codec call each
+    per_sse = torch.zeros(n, dtype=torch.int64, device=dev)
+    for k in range(n):
+        codec.dct_codec(srcs[k], qs_list[k], dst=dsts[k], sse=per_sse[k:k + 1])
+    torch.cuda.synchronize()
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record()
+    for k in range(n):
+        codec.dct_codec(srcs[k], qs_list[k], dst=dsts[k], sse=per_sse[k:k + 1])
+    p1.record()
+    torch.cuda.synchronize()
+    ms_per = p0.elapsed_time(p1)
+    same_sse = bool(np.array_equal(per_sse.cpu().numpy(), sse_batch))
+
+    graph.replay()
+    torch.cuda.synchronize()
+    cores = len(os.sched_getaffinity(0))
+    order = np.argsort(Ws * Hs)
+    sample = sorted(set([int(order[0]), int(order[-1])] +
+                        [int(v) for v in np.random.default_rng(7).choice(n, 14, replace=False)]))
+    parity = True
+    for k in sample:
+        img = srcs[k].cpu().numpy()
+        rec, osse = bands.codec_bands(img, qs_list[k], threads=cores)
+        parity &= bool(osse == int(sse_batch[k]) and np.array_equal(dsts[k].cpu().numpy(), rec))
+    gpx = total_px / (ms * 1e-3) / 1e9
+    ops = OPS_PER_PIXEL * gpx / 1000.0
+    out = {
+        "metric": METRIC, "value": round(gpx, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic (generated on the device)",
+        "config": {"workload": f"{n} grayscale images, W and H uniform on 64..4096, qs in {{2,4,8,16}}, "
+                               f"fused codec R(10,12,12) in one graph-captured launch",
+                   "images": n, "gpixels": round(total_px / 1e9, 3), "chunk": tune.chunk, "grid": tune.grid,
+                   "entry_point": "dct_batch_run"},
+        "tuning_ms": {f"chunk{c}_grid{g}": round(v, 3) for (c, g), v in sorted(tune.table.items())},
+        "per_image_launches": {"ms": round(ms_per, 3), "gpixel_s": round(total_px / (ms_per * 1e-3) / 1e9, 3),
+                               "same_sse": same_sse},
+        "parity": parity, "parity_images": len(sample),
+        "roofline": {"bound": "alu", "achieved": round(ops, 3), "peak": round(INT32_PEAK_TOPS, 2),
+                     "unit": "Tops/s", "frac": round(ops / INT32_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "batch_codec_kernel", "ops_per_pixel": OPS_PER_PIXEL},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,6 +456,9 @@ def main():
         return
     if args.workload == "pareto":
         bench_pareto(args)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
     import numpy as np
     import torch

@@ -57,6 +57,7 @@
 #ifndef DCTCODEC_H
 #define DCTCODEC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #if defined(__GNUC__)
@@ -179,6 +180,44 @@ DCT_API int dct_recipe_list(int32_t *recipes, int32_t capacity);
 /* Constants of the built recipes with n_iter micro-rotations (host outs), as
  * dct_recipe_tables; DCT_ERR_UNSUPPORTED if no built recipe has that n. */
 DCT_API int dct_recipe_tables_n(int32_t n_iter, int32_t *directions, int32_t *gains);
+
+/* One image of a batch (host struct): planes and quality scale as for dct_codec. */
+typedef struct {
+  const uint8_t *src; /* W x H source plane, row pitch src_stride */
+  uint8_t *dst;       /* W x H reconstruction, row pitch dst_stride */
+  int32_t W, H, src_stride, dst_stride;
+  int32_t qs;         /* quality scale of this image, 1..1024 */
+  int32_t reserved;   /* set to 0 */
+} dct_image;
+
+/* The fused codec of dct_codec over a batch of images of any sizes and quality
+ * scales in one kernel launch (the paper codes one image per run, Sec. 3.2 and
+ * Sec. 4; this is the same per-image computation, bit for bit, for many images).
+ * Planning and running are separate so that the run can be captured in a HIP
+ * graph and replayed:
+ *
+ * dct_batch_workspace_size: bytes of device workspace the batch needs with
+ *   `chunk` blocks per workgroup (256 or 512); 0 if any image or argument is
+ *   invalid.
+ * dct_batch_plan: validates the images (host array of n_images), writes the
+ *   batch description into `workspace` (device memory, 256-byte aligned, at
+ *   least the size above, owned by the caller), waits for `stream`, and
+ *   remembers the plan under the workspace address; *total_chunks (host, may be
+ *   NULL) gets the number of workgroup chunks.  Planning a workspace again
+ *   replaces its plan.  Not capturable (it copies from host memory and waits).
+ * dct_batch_run: codes every image of the plan in `workspace`: writes each dst
+ *   plane and overwrites sse_dev[k] (device, n_images uint64) with image k's
+ *   SSE.  grid = 0 launches one workgroup per chunk; grid > 0 launches that many
+ *   workgroups, each walking the chunks with a fixed stride.  Enqueues two
+ *   kernels and nothing else, so it can be captured in a graph.  The images'
+ *   planes must stay valid and unchanged in place between plan and run.
+ *   DCT_ERR_INVALID if the workspace holds no plan.
+ * dct_batch_release: forgets the plan of a workspace (the caller frees it). */
+DCT_API size_t dct_batch_workspace_size(const dct_image *images, int32_t n_images, int32_t chunk);
+DCT_API int dct_batch_plan(const dct_image *images, int32_t n_images, int32_t chunk, void *workspace,
+                           size_t workspace_bytes, int64_t *total_chunks, void *stream);
+DCT_API int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *stream);
+DCT_API int dct_batch_release(const void *workspace);
 
 /* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
  * the samples, fractional bits P of the gain constants. */

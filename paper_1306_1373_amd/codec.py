@@ -50,11 +50,23 @@ _PROTOS = {
     "dct_recipe_supported": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
     "dct_recipe_list": (C.c_int, [C.POINTER(C.c_int32), C.c_int32]),
     "dct_recipe_tables_n": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "dct_batch_workspace_size": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
+    "dct_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
+                                 C.POINTER(C.c_int64), C.c_void_p]),
+    "dct_batch_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dct_batch_release": (C.c_int, [C.c_void_p]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
     "dct_shutdown": (C.c_int, []),
 }
+
+
+class DctImage(C.Structure):
+    """dct_image of the C ABI: one image of a batch."""
+    _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("W", C.c_int32), ("H", C.c_int32),
+                ("src_stride", C.c_int32), ("dst_stride", C.c_int32), ("qs", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class DctError(RuntimeError):
@@ -284,6 +296,59 @@ def dct_rgb_to_ycbcr(rgb, planes=None):
     _check(load().dct_rgb_to_ycbcr(rgb.data_ptr(), int(W), int(H), int(rs), *ptrs, strides.pop(),
                                    _stream(rgb)), "dct_rgb_to_ycbcr")
     return planes
+
+
+class Batch:
+    """A planned batch (dct_batch_plan) and its device workspace; run() codes every
+    image with one launch.  srcs / dsts are 2-D uint8 device planes; qs is an int
+    or one int per image."""
+
+    def __init__(self, srcs, dsts, qs, chunk: int = 512):
+        import torch
+        if len(srcs) != len(dsts) or not srcs:
+            raise ValueError("need matching, non-empty source and destination lists")
+        qs_list = [int(qs)] * len(srcs) if isinstance(qs, int) else [int(q) for q in qs]
+        if len(qs_list) != len(srcs):
+            raise ValueError("one qs per image")
+        arr = (DctImage * len(srcs))()
+        for k, (a, b, q) in enumerate(zip(srcs, dsts, qs_list)):
+            pa, W, H, sa = _plane(a, "src")
+            pb, Wb, Hb, sb = _plane(b, "dst")
+            if (W, H) != (Wb, Hb):
+                raise ValueError(f"image {k}: dst shape does not match src")
+            arr[k] = DctImage(pa, pb, W, H, sa, sb, q, 0)
+        L = load()
+        n = len(srcs)
+        size = L.dct_batch_workspace_size(arr, n, int(chunk))
+        if size == 0:
+            raise DctError(DCT_ERR_INVALID, "dct_batch_workspace_size")
+        dev = srcs[0].device
+        self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        total = C.c_int64()
+        _check(L.dct_batch_plan(arr, n, int(chunk), self._ws_ptr, size, C.byref(total), _stream(srcs[0])),
+               "dct_batch_plan")
+        self.n_images, self.chunk, self.total_chunks = n, int(chunk), total.value
+        self.sse = torch.zeros(n, dtype=torch.int64, device=dev)
+        self._keep = (list(srcs), list(dsts))
+
+    def run(self, grid: int = 0, sse=None):
+        """Code the batch; returns the int64 device tensor of per-image SSEs."""
+        out = self.sse if sse is None else sse
+        _check(load().dct_batch_run(self._ws_ptr, int(grid), out.data_ptr(), _stream(out)), "dct_batch_run")
+        return out
+
+    def release(self):
+        if self._ws_ptr is not None:
+            load().dct_batch_release(self._ws_ptr)
+            self._ws_ptr = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
 
 
 def psnr_from_sse(sse: int, W: int, H: int, peak: float = 255.0) -> float:

@@ -1,0 +1,54 @@
+// batch.hpp -- the fused codec over a batch of images of uneven size in one launch.
+//
+// Each image's blocks are split into chunks of kChunk consecutive blocks (the
+// last chunk of an image padded with dead lanes), so a chunk, and the
+// workgroup that codes it, belongs to one image: the image's quantizer table
+// stays workgroup-uniform, exactly as in the single-image kernel, and every
+// block is coded by the same device function.  A table maps each chunk to its
+// image; workgroups walk the chunks with a fixed stride (a persistent grid when
+// the launch has fewer workgroups than chunks).  Each workgroup adds its SSE to
+// its image's slot with one atomic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace dct {
+
+// One image of a batch, as the kernel reads it (built by the host).
+struct alignas(16) BatchImage {
+  const uint8_t *src;
+  uint8_t *dst;
+  int32_t W, H, src_stride, dst_stride;
+  int32_t bw, nblocks;
+  int64_t first_chunk;  // index of the image's first chunk
+  CodecQuant qa;        // quantizer of the image's qs (default recipe)
+};
+
+// Layout of the batch workspace: a header, the images, then the chunk table.
+struct BatchHeader {
+  int64_t total_chunks;
+  int32_t n_images;
+  int32_t chunk;  // blocks per chunk = threads per workgroup
+  int64_t images_offset, table_offset;  // bytes from the workspace start
+};
+
+template <int kChunk>
+__global__ __launch_bounds__(kChunk) void batch_codec_kernel(const BatchImage *__restrict__ images,
+                                                             const int32_t *__restrict__ chunk_image,
+                                                             int64_t total_chunks,
+                                                             unsigned long long *__restrict__ sse) {
+  for (int64_t c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+    const int im = __builtin_amdgcn_readfirstlane(chunk_image[c]);
+    const BatchImage &d = images[im];
+    const int b = static_cast<int>(c - d.first_chunk) * kChunk + static_cast<int>(threadIdx.x);
+    const uint32_t err = codec_block<DefaultRecipe, false>(d.src, d.W, d.H, d.src_stride, d.bw, d.nblocks, b, d.qa,
+                                                           d.dst, d.dst_stride, nullptr);
+    workgroup_add<kChunk>(err, sse + im);
+  }
+}
+
+}  // namespace dct

@@ -375,16 +375,14 @@ __global__ __launch_bounds__(kBlockThreads) void inverse_kernel(const int16_t *_
   if (p.live) store_block(dst, W, H, stride, p.by, p.bx, p.full, rec);
 }
 
-// a1..a9 fused under recipe RC: one lane per block; only pixels (and optionally
-// the int16 quantized values) touch memory; the SSE goes to *sse by one atomic
-// per workgroup.
+// a1..a9 on block b of one plane under recipe RC, one lane per block: returns
+// the block's SSE (0 for a lane past the last block).  Every lane of the
+// workgroup must call it together (it contains workgroup barriers).
 template <class RC, bool kEmitQ>
-__global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__restrict__ src, int W, int H,
-                                                              int src_stride, int bw, int nblocks, CodecQuant qa,
-                                                              uint8_t *__restrict__ dst, int dst_stride,
-                                                              int16_t *__restrict__ qcoef,
-                                                              unsigned long long *__restrict__ sse) {
-  const int b = blockIdx.x * kBlockThreads + threadIdx.x;
+__device__ __forceinline__ uint32_t codec_block(const uint8_t *__restrict__ src, int W, int H, int src_stride,
+                                                int bw, int nblocks, int b, const CodecQuant &qa,
+                                                uint8_t *__restrict__ dst, int dst_stride,
+                                                int16_t *__restrict__ qcoef) {
   const BlockPos p = block_pos(b, W, H, bw, nblocks);
   uint32_t pix[16] = {};
   if (p.live) load_block(src, W, H, src_stride, p.by, p.bx, p.full, pix);
@@ -422,6 +420,21 @@ __global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__r
     load_block(src, W, H, src_stride, p.by, p.bx, p.full, pix);  // again, for the SSE (cache hit)
     err = block_sse(pix, rec, W, H, p.by, p.bx, p.full);
   }
+  return err;
+}
+
+// a1..a9 fused under recipe RC: one lane per block; only pixels (and optionally
+// the int16 quantized values) touch memory; the SSE goes to *sse by one atomic
+// per workgroup.
+template <class RC, bool kEmitQ>
+__global__ __launch_bounds__(kBlockThreads) void codec_kernel(const uint8_t *__restrict__ src, int W, int H,
+                                                              int src_stride, int bw, int nblocks, CodecQuant qa,
+                                                              uint8_t *__restrict__ dst, int dst_stride,
+                                                              int16_t *__restrict__ qcoef,
+                                                              unsigned long long *__restrict__ sse) {
+  const int b = blockIdx.x * kBlockThreads + threadIdx.x;
+  const uint32_t err =
+      codec_block<RC, kEmitQ>(src, W, H, src_stride, bw, nblocks, b, qa, dst, dst_stride, qcoef);
   workgroup_add<kBlockThreads>(err, sse);
 }
 

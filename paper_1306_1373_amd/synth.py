@@ -82,6 +82,37 @@ def synth_rgb(W: int, H: int, seed: int, sigma: float = 5.0) -> np.ndarray:
     return np.clip(np.rint(rgb), 0, 255).astype(np.uint8)
 
 
+def synth_image_device(W: int, H: int, seed: int, sigma: float, out) -> None:
+    """Write an image of generator G's family into the (H, W) uint8 device tensor
+    ``out``, computed on the device (for batches too large to generate on the
+    host): the same six random sinusoids, gradient and Gaussian noise, with the
+    parameters and the noise drawn from torch's device generator seeded with
+    ``seed``, evaluated in float32, rounded half to even and clipped.  The bytes
+    are deterministic for a given device and torch build, not equal to G's;
+    consumers that compare against the oracle copy them back."""
+    import math
+
+    import torch
+    dev = out.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    u = torch.rand(26, generator=gen, device=dev, dtype=torch.float64).cpu().tolist()
+    x = torch.arange(W, device=dev, dtype=torch.float32)
+    y = torch.arange(H, device=dev, dtype=torch.float32)
+    gx, gy = -40.0 + 80.0 * u[24], -40.0 + 80.0 * u[25]
+    acc = (128.0 + gx * (x / W - 0.5))[None, :] + (gy * (y / H - 0.5))[:, None]
+    for k in range(6):
+        per = math.exp(math.log(4.0) + u[4 * k] * (math.log(128.0) - math.log(4.0)))
+        ang, pha, amp = u[4 * k + 1] * math.pi, u[4 * k + 2] * 2.0 * math.pi, 10.0 + 20.0 * u[4 * k + 3]
+        a = 2.0 * math.pi * math.cos(ang) / per
+        b = 2.0 * math.pi * math.sin(ang) * y / per + pha
+        acc = acc + torch.cos(b)[:, None] * (amp * torch.sin(a * x))[None, :]
+        acc = acc + torch.sin(b)[:, None] * (amp * torch.cos(a * x))[None, :]
+    if sigma > 0:
+        acc = acc + sigma * torch.randn((H, W), generator=gen, device=dev, dtype=torch.float32)
+    out.copy_(torch.clamp(torch.round(acc), 0.0, 255.0).to(torch.uint8))
+
+
 def sigma_for_seed(seed: int) -> float:
     """Noise level of the 8192 x 8192 workload: sigma = 2 + 8 s / 7 for s = 0..7."""
     return 2.0 + 8.0 * (seed % 8) / 7.0

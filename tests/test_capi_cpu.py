@@ -173,3 +173,35 @@ def test_bands_match_whole_image(oracle_mod):
     assert np.array_equal(bands.forward_bands(img, threads=3), oracle_mod.cordic_forward(img))
     assert np.array_equal(bands.inverse_bands(q, 4, 203, 141, threads=3),
                           oracle_mod.cordic_inverse(q, 4, 203, 141))
+
+
+def test_batch_struct_and_validation(lib):
+    assert C.sizeof(codec.DctImage) == 40
+    ok = codec.DctImage(4096, 8192, 16, 8, 16, 16, 4, 0)
+    arr = (codec.DctImage * 2)(ok, ok)
+    assert lib.dct_batch_workspace_size(arr, 2, 512) > 256
+    assert lib.dct_batch_workspace_size(arr, 2, 300) == 0        # chunk must be 256 or 512
+    assert lib.dct_batch_workspace_size(arr, 0, 512) == 0
+    assert lib.dct_batch_workspace_size(None, 2, 512) == 0
+    bad = (codec.DctImage * 1)(codec.DctImage(4096, 8192, 16, 8, 16, 16, 0, 0))   # qs = 0
+    assert lib.dct_batch_workspace_size(bad, 1, 512) == 0
+    bad = (codec.DctImage * 1)(codec.DctImage(4096, 8192, 16, 8, 12, 16, 4, 0))   # stride % 8
+    assert lib.dct_batch_workspace_size(bad, 1, 512) == 0
+    # workspace too small / misaligned: rejected before the device is touched
+    n = C.c_int64()
+    assert lib.dct_batch_plan(arr, 2, 512, C.c_void_p(1 << 20), 16, C.byref(n), None) == codec.DCT_ERR_INVALID
+    assert lib.dct_batch_plan(arr, 2, 512, C.c_void_p((1 << 20) + 8), 1 << 20, C.byref(n), None) == \
+        codec.DCT_ERR_INVALID
+    assert lib.dct_batch_run(C.c_void_p(1 << 20), 0, C.c_void_p(4096), None) == codec.DCT_ERR_INVALID
+    assert lib.dct_batch_release(C.c_void_p(1 << 20)) == codec.DCT_ERR_INVALID
+
+
+def test_batch_layout_sizes(lib):
+    # W x H blocks, padded per image to whole chunks; table of one int32 per chunk
+    imgs = [codec.DctImage(4096, 8192, W, H, ((W + 7) // 8) * 8, ((W + 7) // 8) * 8, 4, 0)
+            for W, H in ((1, 1), (100, 77), (513 * 8, 8))]
+    arr = (codec.DctImage * 3)(*imgs)
+    chunks = 1 + (-(-(13 * 10) // 512)) + (-(-513 // 512))
+    size = lib.dct_batch_workspace_size(arr, 3, 512)
+    img_bytes = -(-3 * 240 // 256) * 256
+    assert size == 256 + img_bytes + 4 * chunks
