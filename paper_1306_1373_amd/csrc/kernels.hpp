@@ -48,7 +48,7 @@
 
 namespace dct {
 
-inline constexpr int kBlockThreads = 512;  // workgroup of the transform kernels (8 waves)
+inline constexpr int kBlockThreads = 256;  // workgroup of the transform kernels (4 waves)
 inline constexpr int kWg = 256;            // workgroup of the elementwise kernels
 
 // Quantizer of the fused codec, indexed by s = u + v (0..14), wave-uniform (SGPRs).
