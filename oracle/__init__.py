@@ -79,6 +79,14 @@ def lib():
         "or_recipe_peaks": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                       C.c_int, C.c_int, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
+        "or_db_nparam": (C.c_int, []),
+        "or_conv3x3": (None, [_f64p, C.c_int, C.c_int, C.c_int, _f64p, C.c_void_p, C.c_int, _f64p]),
+        "or_conv3x3_bwd": (None, [_f64p, C.c_int, C.c_int, C.c_int, _f64p, C.c_int, _f64p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]),
+        "or_db_forward": (None, [_f64p, _f64p, C.c_int, C.c_int, _f64p, C.c_void_p]),
+        "or_db_loss_grad": (C.c_double, [_f64p, _f64p, _f64p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+        "or_adam_step": (None, [_f64p, _f64p, _f64p, _f64p, C.c_long, C.c_double, C.c_double, C.c_double,
+                                C.c_double, C.c_int]),
         "or_loeffler_forward_f64": (None, [_f64p, _f64p]),
         "or_loeffler_inverse_f64": (None, [_f64p, _f64p]),
     }
@@ -367,3 +375,65 @@ def rgb_to_ycbcr(rgb: np.ndarray):
     cr = np.empty((H, W), np.uint8)
     lib().or_rgb_to_ycbcr(_ptr(rgb), W, H, 3 * W, _ptr(y), _ptr(cb), _ptr(cr), W)
     return y, cb, cr
+
+
+# ---- learned deblocking network (deblock.c) ---------------------------------
+
+def db_nparam() -> int:
+    """Number of parameters of the 1-32-32-32-1 network (19105)."""
+    return lib().or_db_nparam()
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def conv3x3(x, w, b=None):
+    """3x3 cross-correlation with zero padding: x (Ci, H, W), w (Co, Ci, 3, 3), b (Co,) -> (Co, H, W)."""
+    x, w = _f64(x), _f64(w)
+    ci, H, W = x.shape
+    co = w.shape[0]
+    y = np.empty((co, H, W), np.float64)
+    bb = None if b is None else _f64(b)
+    lib().or_conv3x3(x, ci, H, W, w, None if bb is None else bb.ctypes.data, co, y)
+    return y
+
+
+def conv3x3_bwd(x, w, gy):
+    """(gx, gw, gb) of a conv layer given dL/dy."""
+    x, w, gy = _f64(x), _f64(w), _f64(gy)
+    ci, H, W = x.shape
+    co = w.shape[0]
+    gx = np.empty_like(x)
+    gw = np.zeros_like(w)
+    gb = np.zeros(co, np.float64)
+    lib().or_conv3x3_bwd(x, ci, H, W, w, co, gy, gx.ctypes.data, gw.ctypes.data, gb.ctypes.data)
+    return gx, gw, gb
+
+
+def db_forward(params, x):
+    """(y, acts) of the network on one image x (H, W) in [0, 1]; acts (3, 32, H, W)."""
+    params, x = _f64(params), _f64(x)
+    H, W = x.shape
+    y = np.empty((H, W), np.float64)
+    acts = np.empty((3, 32, H, W), np.float64)
+    lib().or_db_forward(params, x, H, W, y, acts.ctypes.data)
+    return y, acts
+
+
+def db_loss_grad(params, x, t, want_grad: bool = True):
+    """(loss, grad) of a batch x, t (B, H, W): mean squared error and its gradient."""
+    params, x, t = _f64(params), _f64(x), _f64(t)
+    B, H, W = x.shape
+    grad = np.empty(db_nparam(), np.float64) if want_grad else None
+    loss = lib().or_db_loss_grad(params, x, t, B, H, W, None if grad is None else grad.ctypes.data)
+    return loss, grad
+
+
+def adam_step(p, m, v, g, lr, b1=0.9, b2=0.999, eps=1e-8, step=1):
+    """One Adam step, in place on the float64 arrays p, m, v."""
+    for a in (p, m, v):
+        if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError("p, m, v must be contiguous float64 arrays")
+    g = _f64(g)
+    lib().or_adam_step(p, m, v, g, p.size, lr, b1, b2, eps, step)

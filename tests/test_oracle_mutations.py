@@ -48,15 +48,33 @@ MUTANTS = {
     "truncating_shift": ("if (v % d != 0 && v < 0) q -= 1;", "(void)0;"),
 }
 
+# planted in deblock.c
+DEBLOCK_MUTANTS = {
+    # ReLU gradient mask dropped after the last hidden layer
+    "relu_mask": ("    for (long k = 0; k < DB_C * n; ++k) g2[k] = a3[k] > 0.0 ? g2[k] : 0.0;\n", ""),
+    # convolution (flipped kernel) instead of cross-correlation
+    "flipped_kernel": ("s += w[((long)co * ci_n + ci) * 9 + dy * 3 + dx]",
+                       "s += w[((long)co * ci_n + ci) * 9 + (2 - dy) * 3 + (2 - dx)]"),
+    # the residual connection missing
+    "no_residual": ("  for (long k = 0; k < n; ++k) y[k] += x[k];\n", ""),
+    # Adam without bias correction
+    "adam_no_bias_correction": ("const double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);",
+                                "const double c1 = 1.0, c2 = 1.0;"),
+    # loss gradient without the factor 2
+    "loss_grad_scale": ("const double scale = 2.0 / ((double)B * n);", "const double scale = 1.0 / ((double)B * n);"),
+}
+
 PIN_MODULES = ["tests/test_oracle_exact.py", "tests/test_oracle_recipe.py", "tests/test_oracle_recipe_family.py",
-               "tests/test_oracle_psnr.py", "tests/test_oracle_color.py"]
+               "tests/test_oracle_psnr.py", "tests/test_oracle_color.py", "tests/test_oracle_deblock.py"]
 
 
-def _run_pins_with(src_text, tmp_path):
+def _run_pins_with(src_text, tmp_path, deblock_text=None):
     mutated = tmp_path / "oracle_mut.c"
     mutated.write_text(src_text)
+    mutated_db = tmp_path / "deblock_mut.c"
+    mutated_db.write_text(deblock_text if deblock_text is not None else open(obuild.SRC_DEBLOCK).read())
     lib = tmp_path / "liboracle_mut.so"
-    subprocess.run(["gcc", "-std=c11", "-O1", "-fPIC", "-shared", str(mutated), "-o", str(lib),
+    subprocess.run(["gcc", "-std=c11", "-O1", "-fPIC", "-shared", str(mutated), str(mutated_db), "-o", str(lib),
                     "-lm", "-lpthread"], check=True)
     # run the pin modules in a child process with the mutant loaded in place of the oracle
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -78,4 +96,13 @@ def test_pins_catch_mutant(name, tmp_path):
     src = open(obuild.SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name} not found once"
     r = _run_pins_with(src.replace(old, new), tmp_path)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(DEBLOCK_MUTANTS))
+def test_pins_catch_deblock_mutant(name, tmp_path):
+    old, new = DEBLOCK_MUTANTS[name]
+    src = open(obuild.SRC_DEBLOCK).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found once"
+    r = _run_pins_with(open(obuild.SRC).read(), tmp_path, deblock_text=src.replace(old, new))
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
