@@ -53,12 +53,15 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 64 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=("codec", "precision", "pareto", "batch"), default="codec",
+    ap.add_argument("--workload", choices=("codec", "precision", "pareto", "batch", "deblock"), default="codec",
                     help="codec (default): the fused integer codec at 8192x8192; precision: "
                          "YCbCr + floating-point forms over 256 RGB 2048x2048 images; pareto: "
                          "every built recipe R(n, F, G) at 8192x8192 (one JSON line each)")
     ap.add_argument("--images", type=int, default=256, help="precision workload: images per batch")
     ap.add_argument("--batch-images", type=int, default=10000, help="batch workload: number of images")
+    ap.add_argument("--train-images", type=int, default=2000, help="deblock workload: training images")
+    ap.add_argument("--test-images", type=int, default=500, help="deblock workload: held-out images")
+    ap.add_argument("--train-steps", type=int, default=1500, help="deblock workload: Adam steps")
     ap.add_argument("--distinct", type=int, default=8,
                     help="precision workload: distinct synthetic images, repeated to fill the batch")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -438,6 +441,137 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+DB_SIZE = 1024
+DB_CROP = 64
+DB_BATCH = 32
+DB_VALID = 100
+DB_FLOP_PER_PX = 2.0 * 19105 - 2.0 * 32 * 3 - 2.0   # multiply-adds of the four layers (bias adds excluded)
+
+
+def bench_deblock(args):
+    """The learned form: 1024x1024 synthetic images generated on the device and
+    coded with the batched codec at qs uniform on 8..32; the deblocking network
+    is trained with Adam on random 64x64 crops of the training images, accepted
+    only if it raises PSNR on a validation set (otherwise the output layer is
+    zeroed and the filter returns the decoded image bit for bit), and applied to
+    the held-out images.  Reports the held-out PSNR gain and the filter's
+    Gpixel/s against the codec's own."""
+    import numpy as np
+    import torch
+
+    import oracle as orc
+    from paper_1306_1373_amd import codec
+    from paper_1306_1373_amd.synth import synth_image_device
+
+    codec.load()
+    dev = torch.device("cuda:0")
+    S = DB_SIZE
+    n_tr, n_va, n_te = args.train_images, DB_VALID, args.test_images
+    n_all = n_tr + n_va + n_te
+    rng = np.random.default_rng(77)
+    qs = rng.integers(8, 33, n_all)
+    print(f"[bench] generating and coding {n_all} images of {S}x{S}", file=sys.stderr, flush=True)
+    orig = torch.empty((n_all * S, S), dtype=torch.uint8, device=dev)
+    dec = torch.empty_like(orig)
+    for k in range(n_all):
+        synth_image_device(S, S, 50000 + k, float(rng.uniform(2.0, 8.0)), orig[k * S:(k + 1) * S])
+    batch = codec.Batch([orig[k * S:(k + 1) * S] for k in range(n_all)],
+                        [dec[k * S:(k + 1) * S] for k in range(n_all)], [int(q) for q in qs], chunk=256)
+    sse_plain = batch.run().cpu().numpy()
+    batch.release()
+    torch.cuda.synchronize()
+    t_codec0, t_codec1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # training on crops of the training images
+    db = codec.Deblocker(codec.init_deblock_params(1))
+    steps, B, C = args.train_steps, DB_BATCH, DB_CROP
+    img = rng.integers(0, n_tr, (steps, B))
+    pos = np.stack([img * S + rng.integers(0, S - C + 1, (steps, B)), rng.integers(0, S - C + 1, (steps, B))],
+                   axis=-1).astype(np.int32)
+    pos_dev = torch.from_numpy(pos).to(dev)
+    losses = []
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    for st in range(steps):
+        lr = 2e-3 if st < steps * 0.7 else 5e-4
+        loss = db.train_step(dec, orig, pos_dev[st], C, C, lr=lr)
+        if st % 100 == 0 or st == steps - 1:
+            losses.append(float(loss.cpu()[0]))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - tt0
+
+    def gains(first, count, deblocker):
+        out = codec.new_plane(S, S, dev)
+        g = []
+        for k in range(first, first + count):
+            deblocker.apply(dec[k * S:(k + 1) * S], out=out)
+            _, s = codec.dct_psnr(orig[k * S:(k + 1) * S], out)
+            g.append(codec.psnr_from_sse(s, S, S) - codec.psnr_from_sse(int(sse_plain[k]), S, S))
+        return np.array(g)
+
+    valid_gain = float(gains(n_tr, n_va, db).mean())
+    accepted = valid_gain > 0.0
+    if not accepted:
+        p = db.params.cpu().numpy()
+        p[18816:] = 0.0
+        db = codec.Deblocker(p)
+    test_gain = gains(n_tr + n_va, n_te, db)
+
+    # inference throughput over the held-out images, and the codec's over the same images
+    out_planes = torch.empty((n_te * S, S), dtype=torch.uint8, device=dev)
+    first = n_tr + n_va
+    db.apply(dec[first * S:(first + 1) * S], out=out_planes[:S])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(n_te):
+        db.apply(dec[(first + k) * S:(first + k + 1) * S], out=out_planes[k * S:(k + 1) * S])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_apply = e0.elapsed_time(e1)
+    tb = codec.Batch([orig[(first + k) * S:(first + k + 1) * S] for k in range(n_te)],
+                     [out_planes[k * S:(k + 1) * S] for k in range(n_te)], [int(q) for q in qs[first:]], chunk=256)
+    tb.run()
+    torch.cuda.synchronize()
+    t_codec0.record()
+    tb.run()
+    t_codec1.record()
+    torch.cuda.synchronize()
+    ms_codec = t_codec0.elapsed_time(t_codec1)
+    tb.release()
+    px = n_te * S * S
+    gpx = px / (ms_apply * 1e-3) / 1e9
+    tflops = DB_FLOP_PER_PX * gpx / 1000.0
+
+    # parity: a 128 x 128 crop of the first held-out image against the oracle's forward pass
+    crop = dec[first * S:first * S + 128, :128].cpu().numpy()
+    db_crop = db.forward(dec, torch.tensor([[first * S, 0]], dtype=torch.int32, device=dev), 128, 128)
+    pq = db.params.cpu().numpy().astype(np.float16).astype(np.float64)
+    y_ref, _ = orc.db_forward(pq, crop.astype(np.float64) / 255.0)
+    max_err = float(np.abs(db_crop.cpu().numpy()[0] - y_ref).max())
+    out = {
+        "metric": "held-out PSNR gain (dB) of the learned deblocking filter; its Gpixel/s",
+        "value": round(gpx, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(train_s * 1000.0 / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16 weights and activations, f32 accumulate", "data": "synthetic (device)",
+        "config": {"workload": f"{n_tr} training + {n_va} validation + {n_te} held-out {S}x{S} synthetic images, "
+                               f"codec R(10,12,12) at qs uniform on 8..32; 1-32-32-32-1 3x3 network, Adam on "
+                               f"{B} crops of {C}x{C} per step",
+                   "train_images": n_tr, "valid_images": n_va, "test_images": n_te, "size": S,
+                   "crop": C, "crops_per_step": B, "train_steps": steps},
+        "psnr_gain_db": {"mean": round(float(test_gain.mean()), 4), "min": round(float(test_gain.min()), 4),
+                         "max": round(float(test_gain.max()), 4), "validation_mean": round(valid_gain, 4),
+                         "filter_accepted": accepted},
+        "training": {"seconds": round(train_s, 2), "loss_every_100_steps": [round(v, 7) for v in losses]},
+        "codec_gpixel_s_same_images": round(px / (ms_codec * 1e-3) / 1e9, 2),
+        "parity": {"max_abs_err_vs_oracle_128x128": max_err},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 4), "traffic": None, "kernel": "deblock (4 layers)",
+                     "flop_per_pixel": DB_FLOP_PER_PX},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -459,6 +593,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "deblock":
+        bench_deblock(args)
         return
     import numpy as np
     import torch

@@ -219,6 +219,49 @@ DCT_API int dct_batch_plan(const dct_image *images, int32_t n_images, int32_t ch
 DCT_API int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *stream);
 DCT_API int dct_batch_release(const void *workspace);
 
+/* Learned deblocking post-filter for decoded planes.  The paper's decoded images
+ * carry the blocking of 8x8 transform coding (Sec. 4, Tables 3-4); this network
+ * reduces it after dct_codec.  With x = p / 255 for the decoded pixels p:
+ *   a1 = relu(conv(x; W1, b1))  1 -> 32 channels,  a2 = relu(conv(a1; W2, b2))  32 -> 32,
+ *   a3 = relu(conv(a2; W3, b3)) 32 -> 32,          y = x + conv(a3; W4, b4)     32 -> 1,
+ * conv a 3x3 cross-correlation, zero outside each image; output pixel
+ * clamp(floor(255 y + 1/2), 0, 255).  Parameters: 19105 float32 in the order W1
+ * [32][1][3][3], b1 [32], W2 [32][32][3][3], b2 [32], W3 [32][32][3][3], b3 [32],
+ * W4 [1][32][3][3], b4 [1] (device memory, caller-owned); kernels use them rounded
+ * to FP16, store activations as FP16 and accumulate in FP32.  With W4 and b4 zero
+ * the filter returns its input bit for bit.
+ *
+ * Training works on an image set: n images (crops) of h x w whose top-left corners
+ * are pos[2k], pos[2k+1] (row, col; int32 device array) in planes of plane_w x
+ * plane_h pixels and pitch `stride`; pos = NULL means one image at (0, 0).  Pixels
+ * of a crop outside the plane read as 0.  The loss is the mean over all n h w
+ * pixels of (y - original / 255)^2.
+ *
+ * dct_deblock_nparam: 19105.
+ * dct_deblock_workspace_size: device workspace bytes for npix = n h w pixels
+ *   (training != 0: for dct_deblock_forward / dct_deblock_grad; 0: for
+ *   dct_deblock_apply with npix = W H); 0 if npix is out of range.
+ * dct_deblock_apply: filters one decoded W x H plane into `out`.
+ * dct_deblock_forward: y (float32 device array [n][h][w]) of an image set.
+ * dct_deblock_grad: the gradient of the loss (float32 device array [19105],
+ *   overwritten) and the loss (*loss, one double in device memory).
+ * dct_deblock_adam: one Adam step (bias-corrected, step counted from 1) on the
+ *   parameters with moments m, v (float32 device arrays [19105]) and `grad`.
+ * Workspaces are 256-byte aligned device memory owned by the caller. */
+DCT_API int32_t dct_deblock_nparam(void);
+DCT_API size_t dct_deblock_workspace_size(int64_t npix, int32_t training);
+DCT_API int dct_deblock_apply(const uint8_t *decoded, int32_t W, int32_t H, int32_t stride, const float *params,
+                              uint8_t *out, int32_t out_stride, void *workspace, size_t workspace_bytes, void *stream);
+DCT_API int dct_deblock_forward(const uint8_t *decoded, int32_t plane_w, int32_t plane_h, int32_t stride,
+                                const int32_t *pos, int32_t n, int32_t h, int32_t w, const float *params, float *y,
+                                void *workspace, size_t workspace_bytes, void *stream);
+DCT_API int dct_deblock_grad(const uint8_t *decoded, const uint8_t *original, int32_t plane_w, int32_t plane_h,
+                             int32_t stride, const int32_t *pos, int32_t n, int32_t h, int32_t w,
+                             const float *params, float *grad, double *loss, void *workspace,
+                             size_t workspace_bytes, void *stream);
+DCT_API int dct_deblock_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                             float beta1, float beta2, float eps, void *stream);
+
 /* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
  * the samples, fractional bits P of the gain constants. */
 DCT_API int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits);

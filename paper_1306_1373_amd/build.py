@@ -17,7 +17,7 @@ LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libdctcodec.so")
 SOURCES = [os.path.join(CSRC, "dctcodec.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp", "matrix_form.hpp",
-                                           "batch.hpp")] + [
+                                           "batch.hpp", "deblock.hpp")] + [
     os.path.join(INCLUDE, "dctcodec.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -55,6 +55,18 @@ _PROTOS = {
                                  C.POINTER(C.c_int64), C.c_void_p]),
     "dct_batch_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dct_batch_release": (C.c_int, [C.c_void_p]),
+    "dct_deblock_nparam": (C.c_int32, []),
+    "dct_deblock_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
+    "dct_deblock_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dct_deblock_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_void_p]),
+    "dct_deblock_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dct_deblock_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                   C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
@@ -349,6 +361,104 @@ class Batch:
             self.release()
         except Exception:
             pass
+
+
+class Deblocker:
+    """The learned deblocking post-filter (dct_deblock_*): FP32 master parameters
+    and Adam moments on the device, and workspaces sized on demand.  Crops are
+    given as an int32 device tensor [n, 2] of top-left (row, col) positions in a
+    decoded plane (and the matching original plane) of the same pitch."""
+
+    def __init__(self, params=None, device="cuda"):
+        import numpy as np
+        import torch
+        n = load().dct_deblock_nparam()
+        if params is None:
+            params = init_deblock_params(0)
+        params = np.asarray(params, dtype=np.float32)
+        if params.size != n:
+            raise ValueError(f"expected {n} parameters")
+        self.params = torch.from_numpy(params.copy()).to(device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.step_count = 0
+        self._ws = {}
+
+    def _workspace(self, npix: int, training: bool):
+        import torch
+        key = (int(npix), bool(training))
+        if key not in self._ws:
+            size = load().dct_deblock_workspace_size(int(npix), int(training))
+            if size == 0:
+                raise DctError(DCT_ERR_INVALID, "dct_deblock_workspace_size")
+            buf = torch.empty(size + 256, dtype=torch.uint8, device=self.params.device)
+            off = (-buf.data_ptr()) % 256
+            self._ws = {key: (buf, buf.data_ptr() + off, size)}
+        return self._ws[key]
+
+    def apply(self, decoded, out=None):
+        """The filtered plane (uint8) of a decoded plane."""
+        p, W, H, s = _plane(decoded, "decoded")
+        if out is None:
+            out = new_plane(W, H, decoded.device)
+        po, Wo, Ho, so = _plane(out, "out")
+        if (Wo, Ho) != (W, H):
+            raise ValueError("out shape does not match")
+        _, ws, size = self._workspace(W * H, False)
+        _check(load().dct_deblock_apply(p, W, H, s, self.params.data_ptr(), po, so, ws, size,
+                                        _stream(decoded)), "dct_deblock_apply")
+        return out
+
+    def forward(self, decoded, pos, h: int, w: int):
+        """y (float32, [n, h, w]) of the crops of a decoded plane."""
+        import torch
+        p, W, H, s = _plane(decoded, "decoded")
+        n = 1 if pos is None else int(pos.shape[0])
+        y = torch.empty((n, h, w), dtype=torch.float32, device=decoded.device)
+        _, ws, size = self._workspace(n * h * w, True)
+        _check(load().dct_deblock_forward(p, W, H, s, None if pos is None else pos.data_ptr(), n, h, w,
+                                          self.params.data_ptr(), y.data_ptr(), ws, size, _stream(decoded)),
+               "dct_deblock_forward")
+        return y
+
+    def compute_grad(self, decoded, original, pos, h: int, w: int):
+        """Gradient (into self.grad) and mean squared error (self.loss) of the crops."""
+        p, W, H, s = _plane(decoded, "decoded")
+        po, Wo, Ho, so = _plane(original, "original")
+        if (Wo, Ho, so) != (W, H, s):
+            raise ValueError("decoded and original planes must have the same shape and pitch")
+        n = 1 if pos is None else int(pos.shape[0])
+        _, ws, size = self._workspace(n * h * w, True)
+        _check(load().dct_deblock_grad(p, po, W, H, s, None if pos is None else pos.data_ptr(), n, h, w,
+                                       self.params.data_ptr(), self.grad.data_ptr(), self.loss.data_ptr(), ws,
+                                       size, _stream(decoded)), "dct_deblock_grad")
+        return self.grad, self.loss
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step_count += 1
+        _check(load().dct_deblock_adam(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                       self.grad.data_ptr(), self.step_count, lr, beta1, beta2, eps,
+                                       _stream(self.params)), "dct_deblock_adam")
+
+    def train_step(self, decoded, original, pos, h: int, w: int, lr: float):
+        self.compute_grad(decoded, original, pos, h, w)
+        self.adam(lr)
+        return self.loss
+
+
+def init_deblock_params(seed: int):
+    """Initial parameters: He-normal weights for the three ReLU layers, zero
+    biases, and a zero output layer, so the untrained filter is the identity."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci in ((32, 1), (32, 32), (32, 32)):
+        parts.append(rng.normal(0.0, (2.0 / (9 * ci)) ** 0.5, co * ci * 9))
+        parts.append(np.zeros(co))
+    parts.append(np.zeros(32 * 9 + 1))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def psnr_from_sse(sse: int, W: int, H: int, peak: float = 255.0) -> float:

@@ -205,3 +205,15 @@ def test_batch_layout_sizes(lib):
     size = lib.dct_batch_workspace_size(arr, 3, 512)
     img_bytes = -(-3 * 240 // 256) * 256
     assert size == 256 + img_bytes + 4 * chunks
+
+
+def test_deblock_abi_validation(lib):
+    assert lib.dct_deblock_nparam() == 19105
+    assert lib.dct_deblock_workspace_size(0, 0) == 0
+    assert lib.dct_deblock_workspace_size(1000, 1) > lib.dct_deblock_workspace_size(1000, 0) > 0
+    assert lib.dct_deblock_apply(None, 8, 8, 8, P16, P8, 8, P16, 1 << 20, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_deblock_apply(P8, 8, 8, 8, P16, P8, 8, P16, 16, None) == codec.DCT_ERR_INVALID  # small ws
+    assert lib.dct_deblock_forward(P8, 8, 8, 8, None, 2, 4, 4, P16, P16, P16, 1 << 20, None) == \
+        codec.DCT_ERR_INVALID                                                               # n > 1 needs pos
+    assert lib.dct_deblock_adam(P16, P16, P16, P16, 0, 1e-3, 0.9, 0.999, 1e-8, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_deblock_adam(P16, P16, P16, P16, 1, 1e-3, 1.0, 0.999, 1e-8, None) == codec.DCT_ERR_INVALID
