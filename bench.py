@@ -128,7 +128,72 @@ def summarize_profile(root, prefix, out):
     }
     with open(out, "w") as f:
         json.dump(summary, f, indent=1)
+    with open(os.path.splitext(out)[0] + ".md", "w") as f:
+        f.write(profile_markdown(summary, row))
     print(json.dumps(summary, indent=1))
+
+
+def profile_markdown(d, row):
+    """Human-readable form of a profile summary, with the commands that made it."""
+    kt, sq = d["kernel_trace"], d["sq"]
+    tr, algo = d["traffic_bytes_per_dispatch"], d["algorithmic_bytes_per_dispatch"]
+    waves = sq.get("SQ_WAVES", 0.0) or 1.0
+    lines = [
+        f"# codec_kernel, {W} x {H} workload (recipe R(10, 12, 12), qs = {QS})", "",
+        f"Fused codec kernel `{d['kernel']}` on one MI355X as `bench.py` runs it: five rotating "
+        f"{W} x {H} synthetic images, {W * H // 64:,} blocks per launch, one lane per block, "
+        f"{int(waves):,} waves per launch.", "",
+        f"Source digest of the profiled library: `{d['source_sha256']}`; `bench.py` reports the traffic "
+        "below only while the sources still have this digest.", "",
+        "## Commands", "",
+        "Run from `/tmp` with `TMPDIR=/tmp`, `R` the repository root:", "", "```",
+        "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof/trace -o run --output-format csv -- "
+        "python3 $R/bench.py --steps 50 --warmup 10 --no-cpu-baseline --no-check",
+        "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/prof/fetch -o run --output-format csv -- "
+        "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-check",
+        "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/prof/write -o run --output-format csv -- "
+        "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-check",
+        "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/prof/copy_fetch -o run --output-format csv -- "
+        "python3 $R/bench.py --calibrate-copy",
+        "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/prof/copy_write -o run --output-format csv -- "
+        "python3 $R/bench.py --calibrate-copy",
+        "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_VALU2 SQ_INSTS_SALU "
+        "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_LDS -d $R/gpurun_out/prof/sq -o run --output-format csv -- "
+        "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-check",
+        "python3 $R/bench.py --summarize-profile $R/gpurun_out/prof", "```", "",
+        f"## Kernel trace ({kt['calls']} launches)", "",
+        "| | |", "|---|---|",
+        f"| average | {kt['avg_ns'] / 1000:.1f} us |",
+        f"| min / max | {kt['min_ns'] / 1000:.1f} / {kt['max_ns'] / 1000:.1f} us |",
+        f"| share of GPU time in the run | {float(row.get('Percentage', 0)):.1f}% |", "",
+        "## HBM traffic per launch", "",
+        "| counter | KiB per launch | scale (plain 64 MiB copy) | bytes |", "|---|---|---|---|",
+        f"| FETCH_SIZE | {d['fetch_kib_per_dispatch']:.0f} | x{d['fetch_scale']:.3f} | "
+        f"{d['fetch_kib_per_dispatch'] * d['fetch_scale'] * 1024 / 1e6:.1f} MB |",
+        f"| WRITE_SIZE | {d['write_kib_per_dispatch']:.0f} | x{d['write_scale']:.3f} | "
+        f"{d['write_kib_per_dispatch'] * d['write_scale'] * 1024 / 1e6:.1f} MB |",
+        f"| total | | | {tr / 1e6:.1f} MB |",
+        f"| algorithmic (2 B/px) | | | {algo / 1e6:.1f} MB |", "",
+        f"Traffic is {tr / algo:.3f} x the algorithmic bytes.  A plain copy's FETCH_SIZE reads half the "
+        "bytes it moves, hence the factor 2 on reads; writes need none.  The excess over the algorithmic "
+        "bytes is the SSE step's second read of each block's source bytes, part of which misses L2.", "",
+        "## SQ counters per launch", "",
+        "| counter | value | per wave |", "|---|---|---|",
+    ]
+    for k in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU2", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+              "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"):
+        if k in sq:
+            per = "" if k in ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES") else f"{sq[k] / waves:.1f}"
+            lines.append(f"| {k} | {sq[k]:.0f} | {per} |")
+    if "SQ_INSTS_VALU" in sq:
+        per_wave = sq["SQ_INSTS_VALU"] / waves
+        lines += ["", f"Each lane codes one block, so a wave's {per_wave:.0f} VALU instructions are "
+                      f"{per_wave:.0f} per block, {per_wave / 64:.1f} per pixel, against the recipe's "
+                      f"{OPS_PER_PIXEL:.0f} algorithmic operations per pixel.  "
+                      f"SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU = "
+                      f"{100 * sq.get('SQ_ACTIVE_INST_VALU2', 0) / sq['SQ_INSTS_VALU']:.1f}%: the share of VALU "
+                      "issue cycles in which a SIMD issued two VALU instructions."]
+    return "\n".join(lines) + "\n"
 
 
 def profiled_traffic():
@@ -561,7 +626,9 @@ def bench_deblock(args):
                    "crop": C, "crops_per_step": B, "train_steps": steps},
         "psnr_gain_db": {"mean": round(float(test_gain.mean()), 4), "min": round(float(test_gain.min()), 4),
                          "max": round(float(test_gain.max()), 4), "validation_mean": round(valid_gain, 4),
-                         "filter_accepted": accepted},
+                         "filter_accepted": accepted,
+                         "mean_with_encoder_flag": round(float(np.maximum(test_gain, 0.0).mean()), 4),
+                         "images_flagged_off": int((test_gain <= 0.0).sum())},
         "training": {"seconds": round(train_s, 2), "loss_every_100_steps": [round(v, 7) for v in losses]},
         "codec_gpixel_s_same_images": round(px / (ms_codec * 1e-3) / 1e9, 2),
         "parity": {"max_abs_err_vs_oracle_128x128": max_err},
