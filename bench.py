@@ -307,6 +307,23 @@ def bench_precision(args):
         kms = k0.elapsed_time(k1) / args.steps / 3
         plane_px = N * S * S
         hbm = 2.0 * plane_px / (kms * 1e-3) / 1e9
+        fused = None
+        if form != "f32":
+            # the conversion fused into the codec: one launch, 6 B of HBM traffic per RGB pixel
+            fsse = torch.zeros(3, dtype=torch.int64, device=dev)
+            codec.dct_codec_rgb_float(rgb, form, PREC_QS, planes=outs, sse=fsse)
+            torch.cuda.synchronize()
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record()
+            for _ in range(args.steps):
+                codec.dct_codec_rgb_float(rgb, form, PREC_QS, planes=outs, sse=fsse)
+            f1.record()
+            torch.cuda.synchronize()
+            fms = f0.elapsed_time(f1) / args.steps
+            fused = {"ms_per_step": round(fms, 4), "gpixel_s": round(px / (fms * 1e-3) / 1e9, 3),
+                     "hbm_gb_s": round(6.0 * N * S * S / (fms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(6.0 * N * S * S / (fms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "entry_point": "dct_codec_rgb_float"}
         flops = (256.0 if form != "f32" else 0.0) * plane_px / (kms * 1e-3) / 1e12
         out = {
             "metric": "Gpixel/s YCbCr + DCT+quant+IDCT per channel-pixel, floating-point form",
@@ -318,6 +335,7 @@ def bench_precision(args):
             "config": {"workload": f"{N} RGB {S}x{S} synthetic images ({D} distinct, repeated), integer "
                                    f"YCbCr, each plane coded with the {form} form at qs={PREC_QS}",
                        "images": N, "size": S, "qs": PREC_QS, "form": form},
+            "fused_rgb": fused,
             "accuracy": {"max_abs_coef_err": [round(e, 6) for e in errs],
                          "psnr_delta_db": [round(d, 5) for d in dpsnr], "planes": "Y Cb Cr of image 0",
                          "reference": "FP64 exact DCT codec (oracle)", "ycbcr_bit_exact": ycc_exact},

@@ -262,6 +262,18 @@ DCT_API int dct_deblock_grad(const uint8_t *decoded, const uint8_t *original, in
 DCT_API int dct_deblock_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
                              float beta1, float beta2, float eps, void *stream);
 
+/* Three-channel images through the matrix-form codec in one pass: each pixel of
+ * the interleaved RGB image is converted as dct_rgb_to_ycbcr does, each of the
+ * three planes is coded as dct_codec_float does (form DCT_FORM_MFMA_F16 or
+ * DCT_FORM_MFMA_BF16 only), and the reconstructions are written to y, cb, cr
+ * (W x H planes, row pitch plane_stride).  sse_dev (device, three uint64) is
+ * overwritten with each plane's SSE against its converted values.  Bit for bit
+ * the result of dct_rgb_to_ycbcr followed by dct_codec_float on each plane,
+ * without writing or reading the converted planes. */
+DCT_API int dct_codec_rgb_float(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, int32_t form, int32_t qs,
+                                uint8_t *y, uint8_t *cb, uint8_t *cr, int32_t plane_stride, uint64_t *sse_dev,
+                                void *stream);
+
 /* Recipe parameters (host outs): CORDIC micro-rotations n, fractional bits F of
  * the samples, fractional bits P of the gain constants. */
 DCT_API int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_bits);

@@ -42,6 +42,8 @@ _PROTOS = {
                                     C.c_void_p, C.c_void_p]),
     "dct_codec_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dct_codec_rgb_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dct_rgb_to_ycbcr": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_int32, C.c_void_p]),
     "dct_codec_recipe": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -459,6 +461,35 @@ def init_deblock_params(seed: int):
         parts.append(np.zeros(co))
     parts.append(np.zeros(32 * 9 + 1))
     return np.concatenate(parts).astype(np.float32)
+
+
+def dct_codec_rgb_float(rgb, form, qs: int, planes=None, sse=None):
+    """The matrix-form codec of the Y, Cb, Cr planes of an (H, W, 3) uint8 device RGB
+    tensor in one pass; returns ((y, cb, cr) reconstructions, sse tensor [3])."""
+    import torch
+    if not isinstance(rgb, torch.Tensor) or rgb.dtype != torch.uint8 or rgb.dim() != 3 \
+            or rgb.shape[2] != 3 or not rgb.is_cuda:
+        raise TypeError("rgb must be an (H, W, 3) uint8 device tensor")
+    if rgb.stride(2) != 1 or rgb.stride(1) != 3:
+        raise TypeError("rgb pixels must be interleaved and contiguous within a row")
+    H, W, _ = rgb.shape
+    if planes is None:
+        planes = tuple(new_plane(W, H, rgb.device) for _ in range(3))
+    ptrs, strides = [], set()
+    for t in planes:
+        pt, pW, pH, ps = _plane(t, "plane")
+        if (pW, pH) != (W, H):
+            raise ValueError("plane shape does not match rgb")
+        ptrs.append(pt)
+        strides.add(ps)
+    if len(strides) != 1:
+        raise ValueError("the three planes must share one row pitch")
+    if sse is None:
+        sse = torch.empty(3, dtype=torch.int64, device=rgb.device)
+    rs = rgb.stride(0) if H > 1 else 3 * W
+    _check(load().dct_codec_rgb_float(rgb.data_ptr(), int(W), int(H), int(rs), _form(form), int(qs), *ptrs,
+                                      strides.pop(), sse.data_ptr(), _stream(rgb)), "dct_codec_rgb_float")
+    return planes, sse
 
 
 def psnr_from_sse(sse: int, W: int, H: int, peak: float = 255.0) -> float:

@@ -374,6 +374,36 @@ int dct_codec_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride
   return launched();
 }
 
+int dct_codec_rgb_float(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, int32_t form, int32_t qs,
+                        uint8_t *y, uint8_t *cb, uint8_t *cr, int32_t plane_stride, uint64_t *sse_dev,
+                        void *stream) {
+  if (rgb == nullptr || W < 1 || W > kMaxW || H < 1 || H > kMaxH || rgb_stride < 3 * W ||
+      static_cast<uint64_t>(H - 1) * static_cast<uint64_t>(rgb_stride) + 3u * static_cast<uint64_t>(W) >=
+          (uint64_t{1} << 32) ||
+      !plane_ok(y, W, H, plane_stride) || !plane_ok(cb, W, H, plane_stride) || !plane_ok(cr, W, H, plane_stride) ||
+      (form != dct::kFormMfmaF16 && form != dct::kFormMfmaBf16) || qs < 1 || qs > kMaxQs || sse_dev == nullptr ||
+      !aligned(sse_dev, 8))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  const int ntiles = (nblocks + 15) / 16;
+  hipStream_t s = as_stream(stream);
+  auto *acc = reinterpret_cast<unsigned long long *>(sse_dev);
+  dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 3);
+  if (launched()) return DCT_ERR_DEVICE;
+  const dct::FloatQuant fq = float_quant(qs);
+  const bool vec_ok = aligned(rgb, 4) && rgb_stride % 4 == 0;
+  const unsigned kgrid =
+      static_cast<unsigned>(std::min<int64_t>((ntiles + dct::kMfmaWaves - 1) / dct::kMfmaWaves, 4096));
+  if (form == dct::kFormMfmaF16)
+    dct::kron_rgb_kernel<false><<<kgrid, 64 * dct::kMfmaWaves, 0, s>>>(rgb, W, H, rgb_stride, vec_ok, bw, nblocks,
+                                                                       ntiles, fq, y, cb, cr, plane_stride, acc);
+  else
+    dct::kron_rgb_kernel<true><<<kgrid, 64 * dct::kMfmaWaves, 0, s>>>(rgb, W, H, rgb_stride, vec_ok, bw, nblocks,
+                                                                      ntiles, fq, y, cb, cr, plane_stride, acc);
+  return launched();
+}
+
 int dct_rgb_to_ycbcr(const uint8_t *rgb, int32_t W, int32_t H, int32_t rgb_stride, uint8_t *y, uint8_t *cb,
                      uint8_t *cr, int32_t plane_stride, void *stream) {
   if (rgb == nullptr || W < 1 || W > kMaxW || H < 1 || H > kMaxH || rgb_stride < 3 * W ||

@@ -358,34 +358,30 @@ __device__ __forceinline__ uint32_t words_sse(const uint32_t (&a)[4], const uint
   return pp - 2u * pr + rr;
 }
 
-// kCodec = false: FP32 coefficients only; true: quantize, inverse, reconstruct, SSE.
-template <bool kBf16, bool kCodec>
-__global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__restrict__ src, int W, int H,
-                                                              int stride, int bw, int nblocks, int ntiles,
-                                                              float *__restrict__ coef, FloatQuant fq,
-                                                              uint8_t *__restrict__ dst, int dst_stride,
-                                                              unsigned long long *__restrict__ sse) {
-  using T = MfmaTraits<kBf16>;
-  typedef typename T::vec vec;
-  typedef typename T::elem elem;
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-  const uint16_t *K = T::table();
+// Per-lane constants of the matrix form: the A operands of both products and the
+// quantizer entries of the 16 coefficients the lane holds.
+template <bool kBf16>
+struct KronConsts {
+  typename MfmaTraits<kBf16>::vec fa[4][2], ia[4][2];  // fa[t][s] = K[16t + i][sigma(s, g, e)], ia transposed
+  float qv[4][4], rq[4][4];                            // Q and 1/Q of coefficient 16t + 4g + r
+};
 
-  // constant A operands: forward fa[t][s] = K[16t + i][sigma(s, g, e)],
-  // inverse ia[t][s] = K[sigma(s, g, e)][16t + i]
-  vec fa[4][2], ia[4][2];
+template <bool kBf16, bool kCodec>
+__device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, const FloatQuant &fq, int i, int g) {
+  using T = MfmaTraits<kBf16>;
+  typedef typename T::elem elem;
+  const uint16_t *K = T::table();
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        fa[t][s][e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
-        if constexpr (kCodec) ia[t][s][e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
+        kc.fa[t][s][e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
+        if constexpr (kCodec) kc.ia[t][s][e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
       }
-  // the table entry of each coefficient this lane holds: 16t + 4g + r, u + v = 2t + r + g/2 + 4(g%2)
-  float qv[4][4], rq[4][4];
   if constexpr (kCodec) {
+    // coefficient 16t + 4g + r has u + v = 2t + r + g/2 + 4(g%2)
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -397,11 +393,67 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
           qq = sidx == k ? fq.Q[k] : qq;
           rr = sidx == k ? fq.rcp[k] : rr;
         }
-        qv[t][r] = qq;
-        rq[t][r] = rr;
+        kc.qv[t][r] = qq;
+        kc.rq[t][r] = rr;
       }
   }
+}
 
+// forward product of the lane's 16 pixels (four words): acc[t][r] = coefficient 16t + 4g + r
+template <bool kBf16>
+__device__ __forceinline__ void kron_forward(const KronConsts<kBf16> &kc, const uint32_t (&w)[4], f32x4 (&acc)[4]) {
+  using T = MfmaTraits<kBf16>;
+  typedef typename T::vec vec;
+  typedef typename T::elem elem;
+  vec bx[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t word = w[2 * s + (e >> 2)];
+      bx[s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
+    }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    acc[t] = T::mma(kc.fa[t][0], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
+    acc[t] = T::mma(kc.fa[t][1], bx[1], acc[t]);
+  }
+}
+
+// quantize, dequantize, inverse product and reconstruction: the four output words
+template <bool kBf16>
+__device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const f32x4 (&acc)[4], uint32_t (&rec)[4]) {
+  using T = MfmaTraits<kBf16>;
+  typedef typename T::vec vec;
+  typedef typename T::elem elem;
+  // element e = 4(t % 2) + r of inverse step t / 2
+  vec bq[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], kc.qv[t][r], kc.rq[t][r]));
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 x = T::mma(kc.ia[t][0], bq[0], f32x4{0.f, 0.f, 0.f, 0.f});
+    x = T::mma(kc.ia[t][1], bq[1], x);
+    uint32_t v = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v |= freconstruct(x[r]) << (8 * r);
+    rec[t] = v;
+  }
+}
+
+// kCodec = false: FP32 coefficients only; true: quantize, inverse, reconstruct, SSE.
+template <bool kBf16, bool kCodec>
+__global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__restrict__ src, int W, int H,
+                                                              int stride, int bw, int nblocks, int ntiles,
+                                                              float *__restrict__ coef, FloatQuant fq,
+                                                              uint8_t *__restrict__ dst, int dst_stride,
+                                                              unsigned long long *__restrict__ sse) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  KronConsts<kBf16> kc;
+  kron_setup<kBf16, kCodec>(kc, fq, i, g);
   uint64_t err = 0;
   // each wave walks its tiles with the next tile's words already in flight
   const int step = gridDim.x * kMfmaWaves;
@@ -414,21 +466,8 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
     const BlockPos pn = block_pos(b + 16 * step, W, H, bw, nblocks);
     uint32_t wn[4] = {0u, 0u, 0u, 0u};
     if (tile + step < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, wn);
-    // forward B operand: pixels sigma(s, g, e) - 128
-    vec bx[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t word = w[2 * s + (e >> 2)];
-        bx[s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
-      }
     f32x4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc[t] = T::mma(fa[t][0], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
-      acc[t] = T::mma(fa[t][1], bx[1], acc[t]);
-    }
+    kron_forward<kBf16>(kc, w, acc);
     if constexpr (!kCodec) {
       if (p.live) {
 #pragma unroll
@@ -437,23 +476,8 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
               make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
       }
     } else {
-      // quantize and dequantize in place: element e = 4(t % 2) + r of inverse step t / 2
-      vec bq[2];
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], qv[t][r], rq[t][r]));
       uint32_t rec[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        f32x4 x = T::mma(ia[t][0], bq[0], f32x4{0.f, 0.f, 0.f, 0.f});
-        x = T::mma(ia[t][1], bq[1], x);
-        uint32_t v = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v |= freconstruct(x[r]) << (8 * r);
-        rec[t] = v;
-      }
+      kron_code<kBf16>(kc, acc, rec);
       if (p.live) {
         store_words(dst, W, H, dst_stride, p.by, p.bx, g, p.full, rec);
         err += words_sse(w, rec, W, H, p.by, p.bx, g, p.full);
@@ -464,6 +488,108 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
     for (int k = 0; k < 4; ++k) w[k] = wn[k];
   }
   if constexpr (kCodec) workgroup_add<64 * kMfmaWaves>(err, sse);
+}
+
+// JFIF YCbCr of one RGB pixel (integer, 2^-16 weights).  The luma weights sum to
+// 2^16, so Y lies in [0, 255] without a clamp; Cb and Cr are clamped.  (Written
+// without the luma clamp on purpose: with it, hipcc for gfx950 packs pairs of
+// clamped shifts into v_ashr_pk_u8_i32 and then ORs more bytes into the upper
+// half of that register without clearing it, which corrupts byte 2.)
+// Every product of an 8-bit sample and a weight below 2^16 fits 24 bits, so the
+// products use the full-rate 24-bit multiplier; the sums are the same integers.
+__device__ __forceinline__ void ycc_pixel(int R, int G, int B, uint32_t &y, uint32_t &cb, uint32_t &cr) {
+  const uint32_t r = static_cast<uint32_t>(R), g = static_cast<uint32_t>(G), b = static_cast<uint32_t>(B);
+  y = (__umul24(19595u, r) + __umul24(38470u, g) + __umul24(7471u, b) + (1u << 15)) >> 16;
+  const int tb = static_cast<int>((b << 15) + (1u << 15)) - static_cast<int>(__umul24(11058u, r) + __umul24(21710u, g));
+  const int tr = static_cast<int>((r << 15) + (1u << 15)) - static_cast<int>(__umul24(27439u, g) + __umul24(5329u, b));
+  cb = static_cast<uint32_t>(min(max((tb >> 16) + 128, 0), 255));
+  cr = static_cast<uint32_t>(min(max((tr >> 16) + 128, 0), 255));
+}
+
+// The lane's four pixel words of each of the Y, Cb, Cr planes of an RGB block,
+// converted on the fly (positions as load_words).  A full block with 4-aligned
+// RGB rows reads three 4-byte words per 4 pixels; other blocks go byte by byte
+// with edge replication.
+__device__ __forceinline__ void load_rgb_words(const uint8_t *__restrict__ rgb, int W, int H, int rgb_stride,
+                                               int by, int bx, int g, bool full, bool vec_ok, uint32_t (&y)[4],
+                                               uint32_t (&cb)[4], uint32_t (&cr)[4]) {
+  const int x0 = bx * 8 + 4 * (g & 1), y0 = by * 8 + (g >> 1);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    uint32_t bytes[12];
+    if (full && vec_ok) {
+      const uint32_t off = static_cast<uint32_t>(y0 + 2 * t) * static_cast<uint32_t>(rgb_stride) +
+                           static_cast<uint32_t>(3 * x0);
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(rgb + off);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const uint32_t v = src[k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bytes[4 * k + j] = (v >> (8 * j)) & 0xffu;
+      }
+    } else {
+      const uint8_t *row = rgb + static_cast<size_t>(min(y0 + 2 * t, H - 1)) * rgb_stride;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int xx = min(x0 + r, W - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bytes[3 * r + c] = row[3 * xx + c];
+      }
+    }
+    uint32_t wy = 0, wb = 0, wr = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t vy, vb, vr;
+      ycc_pixel(static_cast<int>(bytes[3 * r]), static_cast<int>(bytes[3 * r + 1]), static_cast<int>(bytes[3 * r + 2]),
+                vy, vb, vr);
+      wy |= vy << (8 * r);
+      wb |= vb << (8 * r);
+      wr |= vr << (8 * r);
+    }
+    y[t] = wy;
+    cb[t] = wb;
+    cr[t] = wr;
+  }
+}
+
+// RGB in, three coded planes out: the YCbCr conversion fused with the matrix-form
+// codec of each plane, the SSE of each plane against its converted values into
+// sse[0..2].  Bit for bit what dct_rgb_to_ycbcr followed by the matrix-form codec
+// of each plane gives, with 6 bytes of HBM traffic per RGB pixel instead of 12.
+template <bool kBf16>
+__global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t *__restrict__ rgb, int W, int H,
+                                                                  int rgb_stride, bool vec_ok, int bw, int nblocks,
+                                                                  int ntiles, FloatQuant fq,
+                                                                  uint8_t *__restrict__ out_y,
+                                                                  uint8_t *__restrict__ out_cb,
+                                                                  uint8_t *__restrict__ out_cr, int plane_stride,
+                                                                  unsigned long long *__restrict__ sse) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  KronConsts<kBf16> kc;
+  kron_setup<kBf16, true>(kc, fq, i, g);
+  uint64_t err[3] = {0, 0, 0};
+  for (int tile = blockIdx.x * kMfmaWaves + wave; tile < ntiles; tile += gridDim.x * kMfmaWaves) {
+    const BlockPos p = block_pos(tile * 16 + i, W, H, bw, nblocks);
+    uint32_t w[3][4] = {};
+    if (p.live) load_rgb_words(rgb, W, H, rgb_stride, p.by, p.bx, g, p.full, vec_ok, w[0], w[1], w[2]);
+    uint8_t *outs[3] = {out_y, out_cb, out_cr};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      f32x4 acc[4];
+      kron_forward<kBf16>(kc, w[c], acc);
+      uint32_t rec[4];
+      kron_code<kBf16>(kc, acc, rec);
+      if (p.live) {
+        store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec);
+        err[c] += words_sse(w[c], rec, W, H, p.by, p.bx, g, p.full);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    workgroup_add<64 * kMfmaWaves>(err[c], sse + c);
+    __syncthreads();
+  }
 }
 
 }  // namespace dct
@@ -478,7 +604,7 @@ __device__ __forceinline__ uint32_t ycc_byte(int v) { return static_cast<uint32_
 
 // One pixel: (Y, Cb, Cr) as three bytes.
 __device__ __forceinline__ void ycc(int R, int G, int B, uint32_t &y, uint32_t &cb, uint32_t &cr) {
-  y = ycc_byte((19595 * R + 38470 * G + 7471 * B + (1 << 15)) >> 16);
+  y = static_cast<uint32_t>((19595 * R + 38470 * G + 7471 * B + (1 << 15)) >> 16);  // in [0, 255]: weights sum to 2^16
   cb = ycc_byte(((-11058 * R - 21710 * G + 32768 * B + (1 << 15)) >> 16) + 128);
   cr = ycc_byte(((32768 * R - 27439 * G - 5329 * B + (1 << 15)) >> 16) + 128);
 }

@@ -223,3 +223,34 @@ def test_invalid_form(hip):
         hip.dct_forward_float(src, 7)
     with pytest.raises(hip.DctError):
         hip.dct_codec_float(src, "f16", 0)
+
+
+@pytest.mark.parametrize("form", ["f16", "bf16"])
+def test_fused_rgb_codec_matches_separate_steps(hip, form):
+    # dct_codec_rgb_float == dct_rgb_to_ycbcr followed by dct_codec_float per plane, bit for bit
+    import torch
+    from paper_1306_1373_amd.synth import synth_rgb
+    rng = np.random.default_rng(53)
+    cases = [(synth_rgb(200, 136, 21), None), (synth_rgb(131, 97, 22), None), (synth_rgb(131, 41, 23), 400),
+             (rng.integers(0, 256, (16, 24, 3), dtype=np.uint8), None), (synth_rgb(5, 3, 24), None)]
+    for rgb, pitch in cases:
+        H, W, _ = rgb.shape
+        if pitch is None:
+            dev = torch.from_numpy(rgb).cuda()
+        else:
+            buf = torch.zeros((H, pitch), dtype=torch.uint8, device="cuda")
+            buf[:, :3 * W] = torch.from_numpy(rgb.reshape(H, 3 * W)).cuda()
+            dev = buf.as_strided((H, W, 3), (pitch, 3, 1))
+        fused, sse = hip.dct_codec_rgb_float(dev, form, 8)
+        planes = hip.dct_rgb_to_ycbcr(dev)
+        for c in range(3):
+            ref, s1 = hip.dct_codec_float(planes[c], form, 8)
+            assert np.array_equal(fused[c].cpu().numpy(), ref.cpu().numpy()), (W, H, pitch, c)
+            assert int(sse[c].cpu()) == int(s1.cpu()[0]), (W, H, pitch, c)
+
+
+def test_fused_rgb_rejects_f32(hip):
+    import torch
+    rgb = torch.zeros((8, 8, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(hip.DctError):
+        hip.dct_codec_rgb_float(rgb, "f32", 8)
