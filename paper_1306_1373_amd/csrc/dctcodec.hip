@@ -501,7 +501,7 @@ int dct_batch_release(const void *workspace) {
 int32_t dct_deblock_nparam(void) { return dct::db::kNParam; }
 
 size_t dct_deblock_workspace_size(int64_t npix, int32_t training) {
-  if (npix < 1 || npix > (int64_t{1} << 31)) return 0;
+  if (npix < 1 || npix >= (int64_t{1} << 31)) return 0;
   const DeblockLayout L = deblock_layout(npix, training != 0);
   return L.bytes;
 }
@@ -513,7 +513,8 @@ int dct_deblock_apply(const uint8_t *decoded, int32_t W, int32_t H, int32_t stri
     return DCT_ERR_INVALID;
   const int64_t npix = static_cast<int64_t>(W) * H;
   const DeblockLayout L = deblock_layout(npix, false);
-  if (workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes) return DCT_ERR_INVALID;
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+    return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
   dct::db::ImageSet set{decoded, nullptr, stride, W, H, nullptr, 1, H, W};
   return deblock_forward(set, npix, params, static_cast<uint8_t *>(workspace), L, out, out_stride, nullptr,
@@ -528,7 +529,7 @@ int dct_deblock_forward(const uint8_t *decoded, int32_t plane_w, int32_t plane_h
     return DCT_ERR_INVALID;
   const int64_t npix = static_cast<int64_t>(n) * h * w;
   const DeblockLayout L = deblock_layout(npix, true);
-  if (npix > (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
     return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
   dct::db::ImageSet set{decoded, decoded, stride, plane_w, plane_h, pos, n, h, w};
@@ -545,7 +546,7 @@ int dct_deblock_grad(const uint8_t *decoded, const uint8_t *original, int32_t pl
     return DCT_ERR_INVALID;
   const int64_t npix = static_cast<int64_t>(n) * h * w;
   const DeblockLayout L = deblock_layout(npix, true);
-  if (npix > (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
     return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
   dct::db::ImageSet set{decoded, original, stride, plane_w, plane_h, pos, n, h, w};
@@ -683,7 +684,8 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   auto *g4 = reinterpret_cast<float *>(ws + L.g4);
   prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
   layer1_kernel<<<px_grid(npix), kThreads, 0, s>>>(set, wq, a1, npix);
-  const int64_t ntiles = (npix + 15) / 16;
+  // tiles of 16 pixels of one image row: ceil(w / 16) per row
+  const int64_t ntiles = static_cast<int64_t>(set.n) * set.h * ((set.w + 15) / 16);
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, a2, npix, ntiles);
   mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, a3, npix, ntiles);

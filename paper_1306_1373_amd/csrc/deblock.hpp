@@ -58,13 +58,15 @@ struct Pix {
   int b, r, c;
 };
 
+// pixel id -> (image, row, column); ids stay below 2^31 (checked on the host), so
+// the divisions are 32-bit
 __device__ __forceinline__ Pix pix_of(const ImageSet &s, int64_t p) {
-  const int64_t hw = static_cast<int64_t>(s.h) * s.w;
+  const uint32_t u = static_cast<uint32_t>(p), hw = static_cast<uint32_t>(s.h) * static_cast<uint32_t>(s.w);
   Pix q;
-  q.b = static_cast<int>(p / hw);
-  const int64_t rem = p - static_cast<int64_t>(q.b) * hw;
-  q.r = static_cast<int>(rem / s.w);
-  q.c = static_cast<int>(rem - static_cast<int64_t>(q.r) * s.w);
+  q.b = static_cast<int>(u / hw);
+  const uint32_t rem = u - static_cast<uint32_t>(q.b) * hw;
+  q.r = static_cast<int>(rem / static_cast<uint32_t>(s.w));
+  q.c = static_cast<int>(rem - static_cast<uint32_t>(q.r) * static_cast<uint32_t>(s.w));
   return q;
 }
 
@@ -127,11 +129,15 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const floa
 // Operands of v_mfma_f32_16x16x32_f16 for tap t and output half m (lane i, g):
 //   A[i][8g+e] = W[16m + i][8g + e][t], B[8g+e][i] = ain[neighbour t of pixel i][8g + e],
 //   D[4g+r][i] = output channel 16m + 4g + r of pixel i.
+// A tile is 16 consecutive pixels of one image row (the last tile of a row may be
+// partly past its end); its image, row and first column are the same for the
+// whole wave and are computed once, in scalar registers.
 __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float16 *__restrict__ ain,
                                                        const _Float16 *__restrict__ wh_layer,
                                                        const float *__restrict__ bias,
                                                        _Float16 *__restrict__ aout, int64_t npix, int64_t ntiles) {
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
   h8 wa[9][2];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -144,11 +150,16 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r) bv[m][r] = bias[16 * m + 4 * g + r];
-  const int64_t step = static_cast<int64_t>(gridDim.x) * (kThreads / 64);
-  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * (kThreads / 64) + wave; tile < ntiles; tile += step) {
-    const int64_t p = tile * 16 + i;
-    const bool live = p < npix;
-    const Pix q = pix_of(s, live ? p : 0);
+  const uint32_t row_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
+  const uint32_t step = gridDim.x * (kThreads / 64);
+  for (uint32_t tile = blockIdx.x * (kThreads / 64) + wave; tile < static_cast<uint32_t>(ntiles); tile += step) {
+    const uint32_t row_id = tile / row_tiles;  // image row over the whole set
+    const int b = static_cast<int>(row_id / static_cast<uint32_t>(s.h));
+    const int r = static_cast<int>(row_id - static_cast<uint32_t>(b) * static_cast<uint32_t>(s.h));
+    const int c = static_cast<int>((tile - row_id * row_tiles) * 16u) + i;
+    const bool live = c < s.w;
+    const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
+    const Pix q{b, r, c};
     f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -168,8 +179,8 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
       for (int m = 0; m < 2; ++m) {
         uint32_t hb[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          hb[r] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[m][r] + bv[m][r], 0.0f)));
+        for (int rr = 0; rr < 4; ++rr)
+          hb[rr] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[m][rr] + bv[m][rr], 0.0f)));
         *reinterpret_cast<uint2 *>(aout + p * kC + 16 * m + 4 * g) =
             make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
       }
