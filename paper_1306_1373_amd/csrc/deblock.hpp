@@ -129,9 +129,13 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const floa
 // Operands of v_mfma_f32_16x16x32_f16 for tap t and output half m (lane i, g):
 //   A[i][8g+e] = W[16m + i][8g + e][t], B[8g+e][i] = ain[neighbour t of pixel i][8g + e],
 //   D[4g+r][i] = output channel 16m + 4g + r of pixel i.
-// A tile is 16 consecutive pixels of one image row (the last tile of a row may be
-// partly past its end); its image, row and first column are the same for the
-// whole wave and are computed once, in scalar registers.
+// A wave computes kRows vertically adjacent tiles of 16 pixels (rows r0 .. r0 +
+// kRows - 1, columns c0 .. c0 + 15 of one image): each of the kRows + 2 input rows
+// x 3 column offsets is loaded once and feeds every output row whose 3x3 window
+// covers it, so a tile needs (kRows + 2) * 3 / kRows loads instead of 9.  The
+// image, row and column of a tile are the same for the whole wave.
+inline constexpr int kRows = 3;
+
 __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float16 *__restrict__ ain,
                                                        const _Float16 *__restrict__ wh_layer,
                                                        const float *__restrict__ bias,
@@ -150,39 +154,57 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r) bv[m][r] = bias[16 * m + 4 * g + r];
-  const uint32_t row_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
+  const uint32_t col_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
+  const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
   const uint32_t step = gridDim.x * (kThreads / 64);
   for (uint32_t tile = blockIdx.x * (kThreads / 64) + wave; tile < static_cast<uint32_t>(ntiles); tile += step) {
-    const uint32_t row_id = tile / row_tiles;  // image row over the whole set
-    const int b = static_cast<int>(row_id / static_cast<uint32_t>(s.h));
-    const int r = static_cast<int>(row_id - static_cast<uint32_t>(b) * static_cast<uint32_t>(s.h));
-    const int c = static_cast<int>((tile - row_id * row_tiles) * 16u) + i;
-    const bool live = c < s.w;
-    const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
-    const Pix q{b, r, c};
-    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+    const uint32_t gid = tile / col_tiles;  // (image, row group) over the whole set
+    const int b = static_cast<int>(gid / row_groups);
+    const int r0 = static_cast<int>(gid - static_cast<uint32_t>(b) * row_groups) * kRows;
+    const int c = static_cast<int>((tile - gid * col_tiles) * 16u) + i;
+    f4 acc[kRows][2];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int64_t nb = live ? nb_id(s, q, t / 3 - 1, t % 3 - 1) : -1;
-      h8 bx;
-      if (nb >= 0) {
-        bx = *reinterpret_cast<const h8 *>(ain + nb * kC + 8 * g);
-      } else {
+    for (int j = 0; j < kRows; ++j) acc[j][0] = acc[j][1] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bx[e] = static_cast<_Float16>(0.0f);
+    for (int k = 0; k < kRows + 2; ++k) {  // input row r0 - 1 + k
+      const int rr = r0 - 1 + k;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int cc = c + dx - 1;
+        h8 bx;
+        if (rr >= 0 && rr < s.h && cc >= 0 && cc < s.w && c < s.w) {
+          const int64_t nb = (static_cast<int64_t>(b) * s.h + rr) * s.w + cc;
+          bx = *reinterpret_cast<const h8 *>(ain + nb * kC + 8 * g);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bx[e] = static_cast<_Float16>(0.0f);
+        }
+        // output row j uses input row r0 - 1 + k as tap row dy = k - j
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+          const int dy = k - j;
+          if (dy >= 0 && dy <= 2) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+              acc[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[dy * 3 + dx][m], bx, acc[j][m], 0, 0, 0);
+          }
+        }
       }
-#pragma unroll
-      for (int m = 0; m < 2; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[t][m], bx, acc[m], 0, 0, 0);
     }
-    if (live) {
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        uint32_t hb[4];
+    for (int j = 0; j < kRows; ++j) {
+      const int r = r0 + j;
+      if (r < s.h && c < s.w) {
+        const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-          hb[rr] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[m][rr] + bv[m][rr], 0.0f)));
-        *reinterpret_cast<uint2 *>(aout + p * kC + 16 * m + 4 * g) =
-            make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+        for (int m = 0; m < 2; ++m) {
+          uint32_t hb[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            hb[q] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][q] + bv[m][q], 0.0f)));
+          *reinterpret_cast<uint2 *>(aout + p * kC + 16 * m + 4 * g) =
+              make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+        }
       }
     }
   }
