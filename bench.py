@@ -105,7 +105,7 @@ def summarize_profile(root, prefix, out):
     import csv
     import glob
 
-    from paper_1306_1373_amd.build import source_digest
+    from paper_1306_1373_amd.build import codec_kernel_digest
     stats = sorted(glob.glob(os.path.join(root, "trace", "**", "*kernel_stats.csv"), recursive=True))[0]
     row = [r for r in csv.DictReader(open(stats)) if r["Name"].startswith(prefix)][0]
     fetch = _counter_means(os.path.join(root, "fetch"), prefix)["FETCH_SIZE"]
@@ -116,7 +116,7 @@ def summarize_profile(root, prefix, out):
     fscale, wscale = COPY_BYTES / 1024 / cfetch, COPY_BYTES / 1024 / cwrite
     summary = {
         "kernel": row["Name"].split("(")[0],
-        "source_sha256": source_digest(),
+        "kernel_sha256": codec_kernel_digest(),
         "kernel_trace": {"calls": int(row["Calls"]), "avg_ns": float(row["AverageNs"]),
                          "min_ns": float(row["MinNs"]), "max_ns": float(row["MaxNs"])},
         "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
@@ -143,8 +143,8 @@ def profile_markdown(d, row):
         f"Fused codec kernel `{d['kernel']}` on one MI355X as `bench.py` runs it: five rotating "
         f"{W} x {H} synthetic images, {W * H // 64:,} blocks per launch, one lane per block, "
         f"{int(waves):,} waves per launch.", "",
-        f"Source digest of the profiled library: `{d['source_sha256']}`; `bench.py` reports the traffic "
-        "below only while the sources still have this digest.", "",
+        f"Digest of the codec kernel's sources and flags when profiled: `{d['kernel_sha256']}`; `bench.py` "
+        "reports the traffic below only while they still have this digest.", "",
         "## Commands", "",
         "Run from `/tmp` with `TMPDIR=/tmp`, `R` the repository root:", "", "```",
         "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof/trace -o run --output-format csv -- "
@@ -198,12 +198,12 @@ def profile_markdown(d, row):
 
 def profiled_traffic():
     """HBM bytes per codec launch from the committed counter summary, or None when the
-    kernel sources have changed since the counters were taken."""
+    codec kernel's sources or flags have changed since the counters were taken."""
     try:
-        from paper_1306_1373_amd.build import source_digest
+        from paper_1306_1373_amd.build import codec_kernel_digest
         with open(PROFILE) as f:
             prof = json.load(f)
-        if prof.get("source_sha256") == source_digest():
+        if prof.get("kernel_sha256") == codec_kernel_digest():
             return round(prof["traffic_bytes_per_dispatch"])
     except (OSError, ValueError, KeyError):
         pass

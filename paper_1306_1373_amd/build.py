@@ -45,6 +45,23 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
+CODEC_KERNEL_FILES = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp")]
+
+
+def codec_kernel_digest() -> str:
+    """SHA-256 over what the fused integer codec kernel is compiled from (its three
+    headers and the compiler flags): a profile of that kernel stays valid while
+    this digest is unchanged, whatever else changes in the library."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in CODEC_KERNEL_FILES:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    h.update(" ".join([HIPCC.rsplit("/", 1)[-1], *FLAGS]).encode())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, extra=None, out: str = LIB) -> str:
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp"
