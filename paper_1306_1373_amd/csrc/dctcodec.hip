@@ -139,7 +139,7 @@ int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, c
                  uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
 
 struct DeblockLayout {
-  size_t wq, wh, sq, a1, a2, a3, g4, ga, gb, bytes;
+  size_t wq, wh, sq, a1, a2, a3, g4, ga, gb, part, bytes;
 };
 DeblockLayout deblock_layout(int64_t npix, bool training);
 int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *params, uint8_t *ws,
@@ -661,6 +661,9 @@ DeblockLayout deblock_layout(int64_t npix, bool training) {
   if (training) o += gsz;
   L.gb = o;
   if (training) o += gsz;
+  // per-workgroup partial weight gradients: at most 1024 workgroups x the largest layer
+  L.part = o;
+  if (training) o += align256(sizeof(float) * 1024 * (dct::db::kC * dct::db::kC * 9 + dct::db::kC));
   L.bytes = o;
   return L;
 }
@@ -689,14 +692,16 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, a2, npix, ntiles);
   mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, a3, npix, ntiles);
+  // layer 4: one thread per kRows vertically adjacent pixels of a column
+  const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
   if (out != nullptr) {
-    layer4_kernel<false><<<px_grid(npix), kThreads, 0, s>>>(set, a3, wq, npix, out, out_stride, nullptr,
-                                                            nullptr, nullptr, 0.0f);
+    layer4_kernel<false><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, out, out_stride, nullptr,
+                                                               nullptr, nullptr, 0.0f);
     return launched();
   }
   zero_f32_kernel<<<1, kThreads, 0, s>>>(reinterpret_cast<float *>(sq), 2);
-  layer4_kernel<true><<<px_grid(npix), kThreads, 0, s>>>(set, a3, wq, npix, nullptr, 0, y, g4, sq,
-                                                         2.0f / static_cast<float>(npix));
+  layer4_kernel<true><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, nullptr, 0, y, g4, sq,
+                                                            2.0f / static_cast<float>(npix));
   if (grad != nullptr) mean_kernel<<<1, 64, 0, s>>>(sq, loss, 1.0 / static_cast<double>(npix));
   return launched();
 }
@@ -713,21 +718,29 @@ int deblock_backward(const dct::db::ImageSet &set, int64_t npix, uint8_t *ws, co
   auto *g4 = reinterpret_cast<float *>(ws + L.g4);
   auto *ga = reinterpret_cast<float *>(ws + L.ga);
   auto *gb = reinterpret_cast<float *>(ws + L.gb);
-  zero_f32_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(grad, kNParam);
+  auto *part = reinterpret_cast<float *>(ws + L.part);
+  // at most 1024 workgroups per reduction, so the partials fit the workspace
   const int per_wg = static_cast<int>(std::max<int64_t>(256, (npix + 1023) / 1024));
-  const unsigned wg = static_cast<unsigned>((npix + per_wg - 1) / per_wg);
+  const int wg = static_cast<int>((npix + per_wg - 1) / per_wg);
   const unsigned pg = px_grid(npix);
+  auto reduce = [&](int nw, int nb, float *dW, float *db) {
+    reduce_kernel<<<grid_for(nw + nb), kThreads, 0, s>>>(part, wg, nw, nb, dW, db);
+  };
   // layer 4
-  wgrad_kernel<kC, 1><<<wg, kThreads, 0, s>>>(set, g4, a3, grad + kW4, grad + kB4, npix, per_wg);
+  wgrad_kernel<kC, 1><<<wg, kThreads, 0, s>>>(set, g4, a3, part, npix, per_wg);
+  reduce(kC * 9, 1, grad + kW4, grad + kB4);
   bwd4_kernel<<<pg, kThreads, 0, s>>>(set, g4, a3, wq, ga, npix);
   // layer 3: ga = dL/d(pre-activation 3)
-  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, ga, a2, grad + kW3, grad + kB3, npix, per_wg);
+  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, ga, a2, part, npix, per_wg);
+  reduce(kC * kC * 9, kC, grad + kW3, grad + kB3);
   bwd_mid_kernel<<<pg, kThreads, 0, s>>>(set, ga, a2, wq + kW3, gb, npix);
   // layer 2
-  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, gb, a1, grad + kW2, grad + kB2, npix, per_wg);
+  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, gb, a1, part, npix, per_wg);
+  reduce(kC * kC * 9, kC, grad + kW2, grad + kB2);
   bwd_mid_kernel<<<pg, kThreads, 0, s>>>(set, gb, a1, wq + kW2, ga, npix);
   // layer 1
-  wgrad_kernel<1, kC><<<wg, kThreads, 0, s>>>(set, ga, nullptr, grad + kW1, grad + kB1, npix, per_wg);
+  wgrad_kernel<1, kC><<<wg, kThreads, 0, s>>>(set, ga, nullptr, part, npix, per_wg);
+  reduce(kC * 9, kC, grad + kW1, grad + kB1);
   return launched();
 }
 

@@ -213,39 +213,68 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
 // y = x + conv(a3; W4, b4).  kTrain = false: writes the output pixel to `out`
 // (clamp(floor(255 y + 1/2))).  kTrain = true: y to y_out (if not null),
 // dL/dy = grad_scale (y - t) to g4, and the sum of (y - t)^2 to *sq (one atomic
-// per wave).
+// per wave).  A thread computes kRows vertically adjacent pixels of one column:
+// each of the kRows + 2 neighbour rows x 3 columns is loaded and converted once.
 template <bool kTrain>
 __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Float16 *__restrict__ a3,
-                                                          const float *__restrict__ wq, int64_t npix,
+                                                          const float *__restrict__ wq, int64_t ngroups,
                                                           uint8_t *__restrict__ out, int out_stride,
                                                           float *__restrict__ y_out, float *__restrict__ g4,
                                                           double *__restrict__ sq, float grad_scale) {
   double local = 0.0;
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; p < npix;
-       p += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const Pix q = pix_of(s, p);
-    float acc = wq[kB4];
+  const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
+  for (int64_t gidx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; gidx < ngroups;
+       gidx += static_cast<int64_t>(gridDim.x) * kThreads) {
+    // group id -> (image, row group, column)
+    const uint32_t u = static_cast<uint32_t>(gidx);
+    const uint32_t col_id = u / static_cast<uint32_t>(s.w);
+    const int c = static_cast<int>(u - col_id * static_cast<uint32_t>(s.w));
+    const int b = static_cast<int>(col_id / row_groups);
+    const int r0 = static_cast<int>(col_id - static_cast<uint32_t>(b) * row_groups) * kRows;
+    float acc[kRows];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int64_t nb = nb_id(s, q, t / 3 - 1, t % 3 - 1);
-      if (nb < 0) continue;
-      const uint4 *src = reinterpret_cast<const uint4 *>(a3 + nb * kC);
+    for (int j = 0; j < kRows; ++j) acc[j] = wq[kB4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const h8 hv = __builtin_bit_cast(h8, src[k]);
+    for (int k = 0; k < kRows + 2; ++k) {  // input row r0 - 1 + k
+      const int rr = r0 - 1 + k;
+      if (rr < 0 || rr >= s.h) continue;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc += wq[kW4 + (8 * k + e) * 9 + t] * static_cast<float>(hv[e]);
+      for (int dx = 0; dx < 3; ++dx) {
+        const int cc = c + dx - 1;
+        if (cc < 0 || cc >= s.w) continue;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a3 + ((static_cast<int64_t>(b) * s.h + rr) * s.w + cc) * kC);
+        float av[kC];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const h8 hv = __builtin_bit_cast(h8, src[q]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) av[8 * q + e] = static_cast<float>(hv[e]);
+        }
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+          const int dy = k - j;  // tap row of output row r0 + j
+          if (dy >= 0 && dy <= 2) {
+#pragma unroll
+            for (int ci = 0; ci < kC; ++ci) acc[j] += wq[kW4 + ci * 9 + dy * 3 + dx] * av[ci];
+          }
+        }
       }
     }
-    const float y = plane_px(s, s.plane, q.b, q.r, q.c) * kInv255 + acc;
-    if constexpr (!kTrain) {
-      const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
-      out[static_cast<size_t>(q.r) * out_stride + q.c] = static_cast<uint8_t>(v);
-    } else {
-      const float e = y - plane_px(s, s.orig, q.b, q.r, q.c) * kInv255;
-      if (y_out) y_out[p] = y;
-      g4[p] = grad_scale * e;
-      local += static_cast<double>(e) * e;
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const int r = r0 + j;
+      if (r >= s.h) break;
+      const float y = plane_px(s, s.plane, b, r, c) * kInv255 + acc[j];
+      const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
+      if constexpr (!kTrain) {
+        const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
+        out[static_cast<size_t>(r) * out_stride + c] = static_cast<uint8_t>(v);
+      } else {
+        const float e = y - plane_px(s, s.orig, b, r, c) * kInv255;
+        if (y_out) y_out[p] = y;
+        g4[p] = grad_scale * e;
+        local += static_cast<double>(e) * e;
+      }
     }
   }
   if constexpr (kTrain) {
@@ -332,18 +361,20 @@ __global__ __launch_bounds__(kThreads) void bwd_mid_kernel(ImageSet s, const flo
   }
 }
 
-// Weight and bias gradients of one layer, added into dW [CO][CI][9] and db [CO]:
+// Weight and bias gradients of one layer, first stage:
 //   dW[co][ci][t] = sum_p gout[p][co] in[p + offset(t)][ci],  db[co] = sum_p gout[p][co],
 // with `in` the FP16 activations (CI = 32) or the decoded plane / 255 (CI = 1).
-// Thread k of the workgroup owns co = k / GROUPS and CPT = CI / GROUPS input
-// channels; each workgroup reduces `per_wg` consecutive pixels, then adds its
-// partial sums with atomics.
+// Workgroup w sums `per_wg` consecutive pixels and writes its partial sums to
+// part[w][0 .. CO CI 9 + CO) (weights, then biases); reduce_kernel adds the
+// partials of all workgroups.  Thread k owns co = k / GROUPS and CPT = CI / GROUPS
+// input channels.
 template <int CI, int CO>
 __global__ __launch_bounds__(kThreads) void wgrad_kernel(ImageSet s, const float *__restrict__ gout,
-                                                         const _Float16 *__restrict__ ain, float *__restrict__ dW,
-                                                         float *__restrict__ db, int64_t npix, int per_wg) {
+                                                         const _Float16 *__restrict__ ain, float *__restrict__ part,
+                                                         int64_t npix, int per_wg) {
   constexpr int GROUPS = CI >= 4 ? (kThreads / CO < CI / 4 ? kThreads / CO : CI / 4) : 1;
   constexpr int CPT = CI / GROUPS;
+  constexpr int NW = CO * CI * 9 + CO;
   static_assert(CO * GROUPS <= kThreads, "one thread per (co, group)");
   const int k = threadIdx.x;
   const bool active = k < CO * GROUPS;
@@ -375,11 +406,27 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(ImageSet s, const float
         }
       }
     }
+    float *dst = part + static_cast<size_t>(blockIdx.x) * NW;
 #pragma unroll
     for (int j = 0; j < CPT; ++j)
 #pragma unroll
-      for (int t = 0; t < 9; ++t) atomicAdd(dW + (co * CI + grp * CPT + j) * 9 + t, acc[j][t]);
-    if (grp == 0) atomicAdd(db + co, accb);
+      for (int t = 0; t < 9; ++t) dst[(co * CI + grp * CPT + j) * 9 + t] = acc[j][t];
+    if (grp == 0) dst[CO * CI * 9 + co] = accb;
+  }
+}
+
+// Second stage: dW[k] = sum over workgroups of part[w][k] for the nw weights,
+// db[k] likewise for the nb biases stored after them.
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restrict__ part, int nwg, int nw, int nb,
+                                                          float *__restrict__ dW, float *__restrict__ db) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k < nw + nb) {
+    float acc = 0.0f;
+    for (int w = 0; w < nwg; ++w) acc += part[static_cast<size_t>(w) * (nw + nb) + k];
+    if (k < nw)
+      dW[k] = acc;
+    else
+      db[k - nw] = acc;
   }
 }
 
