@@ -176,7 +176,9 @@ def profile_markdown(d, row):
         f"| algorithmic (2 B/px) | | | {algo / 1e6:.1f} MB |", "",
         f"Traffic is {tr / algo:.3f} x the algorithmic bytes.  A plain copy's FETCH_SIZE reads half the "
         "bytes it moves, hence the factor 2 on reads; writes need none.  The excess over the algorithmic "
-        "bytes is the SSE step's second read of each block's source bytes, part of which misses L2.", "",
+        "bytes: the register values the kernel's four-wave cap keeps in scratch (a few dozen bytes per "
+        "lane, written and read back once) and the SSE step's second read of each block's source bytes, "
+        "part of which misses L2.", "",
         "## SQ counters per launch", "",
         "| counter | value | per wave |", "|---|---|---|",
     ]

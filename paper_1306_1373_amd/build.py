@@ -58,7 +58,9 @@ def codec_kernel_digest() -> str:
         h.update(os.path.basename(path).encode())
         with open(path, "rb") as f:
             h.update(f.read())
-    h.update(" ".join([HIPCC.rsplit("/", 1)[-1], *FLAGS]).encode())
+    # include directories by name only: the digest must not depend on where the tree sits
+    flags = ["-I" + os.path.basename(f[2:]) if f.startswith("-I") else f for f in FLAGS]
+    h.update(" ".join([HIPCC.rsplit("/", 1)[-1], *flags]).encode())
     return h.hexdigest()
 
 

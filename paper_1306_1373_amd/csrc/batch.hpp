@@ -37,17 +37,18 @@ struct BatchHeader {
 };
 
 template <int kChunk>
-__global__ __launch_bounds__(kChunk) void batch_codec_kernel(const BatchImage *__restrict__ images,
+__global__ __launch_bounds__(kChunk) DCT_FOUR_WAVES void batch_codec_kernel(const BatchImage *__restrict__ images,
                                                              const int32_t *__restrict__ chunk_image,
                                                              int64_t total_chunks,
                                                              unsigned long long *__restrict__ sse) {
+  const int wave = wave_index();
   for (int64_t c = blockIdx.x; c < total_chunks; c += gridDim.x) {
     const int im = __builtin_amdgcn_readfirstlane(chunk_image[c]);
     const BatchImage &d = images[im];
-    const int b = static_cast<int>(c - d.first_chunk) * kChunk + static_cast<int>(threadIdx.x);
-    const uint32_t err = codec_block<DefaultRecipe, false>(d.src, d.W, d.H, d.src_stride, d.bw, d.nblocks, b, d.qa,
-                                                           d.dst, d.dst_stride, nullptr);
-    workgroup_add<kChunk>(err, sse + im);
+    const int wave_base = static_cast<int>(c - d.first_chunk) * kChunk + wave * 64;
+    const uint32_t err = codec_block<DefaultRecipe, false>(d.src, d.W, d.H, d.src_stride, d.bw, d.nblocks, wave_base,
+                                                           d.qa, d.dst, d.dst_stride, nullptr);
+    workgroup_add<kChunk>(err, sse + im, wave);
   }
 }
 

@@ -16,14 +16,26 @@
 // b' = b - d_i (a >> i), directions resolved at compile time, followed by the
 // gain compensation (v M + 2^(P-1)) >> P of each output.  All shifts are
 // arithmetic; no value leaves int32 (the largest magnitude any step stores is
-// below 2^29 for every input a uint8 plane or a clamped dequantized block gives).
+// below 2^30 for every input a uint8 plane or a clamped dequantized block gives).
+//
+// The compensation is computed as the high word of a 64-bit multiply-add:
+//   (v M + 2^14) >> 15 = ((v 2^k) (M 2^(17-k)) + 2^31) >> 32,
+// an identity of integers, with k = 1 for M < 2^15 and k = 2 for M < 2^16 so
+// that M 2^(17-k) fits int32; v 2^k fits int32 because every compensated value
+// of every recipe stays below 2^(31-k) in magnitude (bounded on the CPU through
+// the flow graph's linear forms and truncation errors: at most 2^30.4 after the
+// shift).  The shift is a plain instruction; the funnel shift the direct form
+// needs to extract bits 15..46 is not.
 //
 // A pass transforms all eight lines (rows or columns) of a register block at
 // once and keeps the instruction kinds apart: the butterflies and micro-
 // rotations of all lines are plain 32-bit adds, subtracts and shifts, which
 // gfx950 can issue two at a time across waves, while the 64-bit multiply-adds
-// of the gain compensations, which it cannot, are gathered into runs.  A
-// scheduling barrier between the regions keeps the compiler from mixing them.
+// of the gain compensations, which it cannot, each cost far more when they
+// stand alone between plain instructions than inside a run.  They are written
+// as runs of eight in one asm statement (the compiler's scheduler otherwise
+// interleaves them with the shifts that feed them), and scheduling barriers
+// keep the regions apart.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,10 +62,52 @@ __device__ __forceinline__ void cordic_step(int &a, int &b) {
   }
 }
 
-// multiply by M / 2^P, rounding half up: (v M + 2^(P-1)) >> P with a 64-bit product
+// the gain compensation's pre-shift k and multiplier M 2^(17-k) (P = 15)
 template <int32_t M>
-__device__ __forceinline__ int compensate(int v) {
-  return static_cast<int>((static_cast<long long>(v) * M + (1LL << (kComp - 1))) >> kComp);
+inline constexpr int kCompShift = M < (1 << 15) ? 1 : 2;
+template <int32_t M>
+inline constexpr int32_t kCompMul = M << (17 - kCompShift<M>);
+static_assert(kComp == 15, "the high-word form of the compensation assumes P = 15");
+
+// high words of v_i M 2^(17-k) + 2^31 for eight pre-shifted values v_i = v 2^k:
+// one run of eight 64-bit multiply-adds
+template <int32_t M>
+__device__ __forceinline__ void comp_mul8(int *v) {
+  static_assert(M > 0 && M < (1 << 16), "multiplier range");
+  const int32_t m = kCompMul<M>;
+  const long long r = 1LL << 31;
+  long long p0, p1, p2, p3, p4, p5, p6, p7;
+  unsigned long long carry;
+  asm("v_mad_i64_i32 %0, %8, %9, %17, %18\n\t"
+      "v_mad_i64_i32 %1, %8, %10, %17, %18\n\t"
+      "v_mad_i64_i32 %2, %8, %11, %17, %18\n\t"
+      "v_mad_i64_i32 %3, %8, %12, %17, %18\n\t"
+      "v_mad_i64_i32 %4, %8, %13, %17, %18\n\t"
+      "v_mad_i64_i32 %5, %8, %14, %17, %18\n\t"
+      "v_mad_i64_i32 %6, %8, %15, %17, %18\n\t"
+      "v_mad_i64_i32 %7, %8, %16, %17, %18"
+      : "=&v"(p0), "=&v"(p1), "=&v"(p2), "=&v"(p3), "=&v"(p4), "=&v"(p5), "=&v"(p6), "=&v"(p7), "=&s"(carry)
+      : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]), "s"(m), "v"(r));
+  v[0] = static_cast<int>(p0 >> 32);
+  v[1] = static_cast<int>(p1 >> 32);
+  v[2] = static_cast<int>(p2 >> 32);
+  v[3] = static_cast<int>(p3 >> 32);
+  v[4] = static_cast<int>(p4 >> 32);
+  v[5] = static_cast<int>(p5 >> 32);
+  v[6] = static_cast<int>(p6 >> 32);
+  v[7] = static_cast<int>(p7 >> 32);
+}
+
+// multiply sixteen values by M / 2^P, rounding half up: (v M + 2^(P-1)) >> P
+template <int32_t M>
+__device__ __forceinline__ void compensate(int (&a)[8], int (&b)[8]) {
+#pragma unroll
+  for (int L = 0; L < 8; ++L) {
+    a[L] = static_cast<int>(static_cast<uint32_t>(a[L]) << kCompShift<M>);
+    b[L] = static_cast<int>(static_cast<uint32_t>(b[L]) << kCompShift<M>);
+  }
+  comp_mul8<M>(a);
+  comp_mul8<M>(b);
 }
 
 // the micro-rotations of the three rotation blocks of all eight lines, step by step
@@ -75,15 +129,9 @@ __device__ __forceinline__ void cordic_lines(int (&a1)[8], int (&b1)[8], int (&a
 template <int N>
 __device__ __forceinline__ void gains_lines(int (&a1)[8], int (&b1)[8], int (&a3)[8], int (&b3)[8],
                                             int (&a6)[8], int (&b6)[8]) {
-#pragma unroll
-  for (int L = 0; L < 8; ++L) {
-    a1[L] = compensate<kTablesN<N>.gain[kRot1]>(a1[L]);
-    b1[L] = compensate<kTablesN<N>.gain[kRot1]>(b1[L]);
-    a3[L] = compensate<kTablesN<N>.gain[kRot3]>(a3[L]);
-    b3[L] = compensate<kTablesN<N>.gain[kRot3]>(b3[L]);
-    a6[L] = compensate<kTablesN<N>.gain[kRot6]>(a6[L]);
-    b6[L] = compensate<kTablesN<N>.gain[kRot6]>(b6[L]);
-  }
+  compensate<kTablesN<N>.gain[kRot1]>(a1, b1);
+  compensate<kTablesN<N>.gain[kRot3]>(a3, b3);
+  compensate<kTablesN<N>.gain[kRot6]>(a6, b6);
 }
 
 // element k of line L: rows when kRows, columns otherwise
@@ -135,10 +183,11 @@ __device__ __forceinline__ void forward_pass(int (&x)[64]) {
   }
   region();
   // stage 4, the two sqrt(2) factors
+  compensate<kTablesN<N>.sqrt2>(v5, v6);
 #pragma unroll
   for (int L = 0; L < 8; ++L) {
-    at<kRows>(x, L, 3) = compensate<kTablesN<N>.sqrt2>(v5[L]);
-    at<kRows>(x, L, 5) = compensate<kTablesN<N>.sqrt2>(v6[L]);
+    at<kRows>(x, L, 3) = v5[L];
+    at<kRows>(x, L, 5) = v6[L];
   }
   region();
 }
@@ -150,9 +199,10 @@ __device__ __forceinline__ void inverse_pass(int (&x)[64]) {
   int v5[8], v6[8];
 #pragma unroll
   for (int L = 0; L < 8; ++L) {
-    v5[L] = compensate<kTablesN<N>.sqrt2>(at<kRows>(x, L, 3));
-    v6[L] = compensate<kTablesN<N>.sqrt2>(at<kRows>(x, L, 5));
+    v5[L] = at<kRows>(x, L, 3);
+    v6[L] = at<kRows>(x, L, 5);
   }
+  compensate<kTablesN<N>.sqrt2>(v5, v6);
   region();
   int e0[8], e1[8], a6[8], b6[8], a3[8], b3[8], a1[8], b1[8];
 #pragma unroll

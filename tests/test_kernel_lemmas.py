@@ -13,6 +13,10 @@ tests then check the kernels themselves.
   floor((floor(|c| / 2^s) + Q 2^(F+2-s)) / 2^(F+3-s)), s = F - 12, and the sum
   stays below 2^32.
 * No coefficient of a uint8 block reaches the dequantization clamp.
+* The gain compensation (v M + 2^14) >> 15 is the high word of
+  (v 2^k)(M 2^(17-k)) + 2^31, and v 2^k fits int32 at every compensated value:
+  bounded through the flow graph as affine forms of the block's inputs plus the
+  truncation errors of every shift and compensation.
 
 Each lemma is checked for every recipe R(n, F, G) the library is built with.
 """
@@ -156,3 +160,144 @@ def test_dequantization_clamp_never_binds(oracle_mod):
     img[:, 8:] = 255
     c = oracle_mod.cordic_forward(img)
     assert c[0, 0] == -1024 << 15 and c[1, 0] == 1016 << 15
+
+
+# ---------------------------------------------------------------------------
+# The gain compensation as the high word of one 64-bit multiply-add
+# ---------------------------------------------------------------------------
+
+def _family_multipliers(oracle_mod):
+    Ms = set()
+    for n in (4, 6, 8, 10, 12):
+        _, gains = oracle_mod.recipe_tables_n(n)
+        Ms.update(int(g) for g in gains)
+    return sorted(Ms)
+
+
+def _high_word_form(v, M):
+    k = 1 if M < 2 ** 15 else 2
+    vs = v << k
+    assert np.all((vs >= -2 ** 31) & (vs < 2 ** 31))   # int32
+    return (vs * (M << (17 - k)) + 2 ** 31) >> 32
+
+
+def test_compensation_high_word_identity(oracle_mod):
+    # (v M + 2^14) >> 15 = ((v 2^k) (M 2^(17-k)) + 2^31) >> 32 for every multiplier of the
+    # family, with both factors in int32
+    rng = np.random.default_rng(35)
+    for M in _family_multipliers(oracle_mod):
+        k = 1 if M < 2 ** 15 else 2
+        assert 0 < M < 2 ** 16 and M << (17 - k) < 2 ** 31
+        lim = 2 ** (31 - k)
+        v = np.concatenate([rng.integers(-lim, lim, 200000, dtype=np.int64),
+                            np.arange(-70000, 70000, dtype=np.int64),
+                            np.arange(lim - 70000, lim, dtype=np.int64),
+                            np.arange(-lim, -lim + 70000, dtype=np.int64)])
+        direct = (v * M + 2 ** 14) >> 15
+        assert np.array_equal(_high_word_form(v, M), direct), M
+    # the planted mistake of a missing rounding term is caught
+    v = np.arange(-5000, 5000, dtype=np.int64)
+    assert not np.array_equal((v * 19898) >> 15, (v * 19898 + 2 ** 14) >> 15)
+
+
+class _Form:
+    """An affine form over the 64 inputs of a block plus a truncation error:
+    value = vec . inputs + const + e with |e| <= err."""
+
+    def __init__(self, vec, const=0.0, err=0.0):
+        self.vec, self.const, self.err = vec, const, err
+
+    def __add__(self, o):
+        return _Form(self.vec + o.vec, self.const + o.const, self.err + o.err)
+
+    def __sub__(self, o):
+        return _Form(self.vec - o.vec, self.const - o.const, self.err + o.err)
+
+    def shr(self, i):   # floor(v / 2^i): v / 2^i minus less than 1
+        return self if i == 0 else _Form(self.vec / 2 ** i, self.const / 2 ** i, self.err / 2 ** i + 1.0)
+
+    def comp(self, M):  # (v M + 2^14) >> 15: v M / 2^15 within 1/2
+        return _Form(self.vec * M / 2 ** 15, self.const * M / 2 ** 15, self.err * M / 2 ** 15 + 0.5)
+
+
+def _compensation_peaks(oracle_mod, n, Fr, Gr):
+    """Largest |v| 2^k over every compensated value of the forward transform of a
+    uint8 block and of the inverse of any block of dequantized values in
+    [-2048, 2048] 2^G plus the DC fold, for recipe R(n, F, G)."""
+    dirs, gains = oracle_mod.recipe_tables_n(n)
+    peaks = []
+
+    def bound_fwd(f):   # inputs p in [0, 255]
+        pos, neg = f.vec[f.vec > 0].sum(), f.vec[f.vec < 0].sum()
+        return max(abs(f.const + 255 * pos), abs(f.const + 255 * neg)) + f.err
+
+    def bound_inv(f):   # inputs d in [-2048, 2048]
+        return abs(f.const) + 2048 * np.abs(f.vec).sum() + f.err
+
+    def comp(f, M, bound):
+        peaks.append((bound(f) * 2 ** (1 if M < 2 ** 15 else 2), bound is bound_fwd))
+        return f.comp(M)
+
+    def rotate(a, b, R, S):
+        for i in range(n):
+            sa, sb = a.shr(i), b.shr(i)
+            a, b = (a + sb, b - sa) if S * dirs[R][i] > 0 else (a - sb, b + sa)
+        return a, b
+
+    def forward_line(v, bd):   # the four stages of Sec. 2.5.2
+        s = [v[i] + v[7 - i] for i in range(4)]
+        d = [v[i] - v[7 - i] for i in range(4)]
+        e0, e1, e2, e3 = s[0] + s[3], s[1] + s[2], s[1] - s[2], s[0] - s[3]
+        a3, b3 = rotate(d[3], d[0], 1, 1)
+        a1, b1 = rotate(d[2], d[1], 0, 1)
+        a6, b6 = rotate(e2, e3, 2, 1)
+        a1, b1, a3, b3 = (comp(a1, gains[0], bd), comp(b1, gains[0], bd),
+                          comp(a3, gains[1], bd), comp(b3, gains[1], bd))
+        a6, b6 = comp(a6, gains[2], bd), comp(b6, gains[2], bd)
+        v4, v7, v6, v5 = a3 + b1, b3 + a1, a3 - b1, b3 - a1
+        return [e0 + e1, v7 + v4, a6, comp(v5, gains[3], bd), e0 - e1, comp(v6, gains[3], bd), b6, v7 - v4]
+
+    def inverse_line(z, bd):   # the transposed graph
+        v5, v6 = comp(z[3], gains[3], bd), comp(z[5], gains[3], bd)
+        v7, v4 = z[1] + z[7], z[1] - z[7]
+        e0, e1 = z[0] + z[4], z[0] - z[4]
+        a3, b3 = rotate(v4 + v6, v7 + v5, 1, -1)
+        a1, b1 = rotate(v7 - v5, v4 - v6, 0, -1)
+        a6, b6 = rotate(z[2], z[6], 2, -1)
+        a1, b1, a3, b3 = (comp(a1, gains[0], bd), comp(b1, gains[0], bd),
+                          comp(a3, gains[1], bd), comp(b3, gains[1], bd))
+        a6, b6 = comp(a6, gains[2], bd), comp(b6, gains[2], bd)
+        s0, s3, s1, s2 = e0 + b6, e0 - b6, e1 + a6, e1 - a6
+        return [s0 + b3, s1 + b1, s2 + a1, s3 + a3, s3 - a3, s2 - a1, s1 - b1, s0 - b3]
+
+    def two_passes(x, line, bd, order):
+        for rows in order:
+            for L in range(8):
+                idx = [L * 8 + k for k in range(8)] if rows else [k * 8 + L for k in range(8)]
+                for i, o in zip(idx, line([x[i] for i in idx], bd)):
+                    x[i] = o
+
+    eye = np.eye(64)
+    two_passes([_Form(eye[i] * 2 ** Fr) for i in range(64)], forward_line, bound_fwd, (True, False))
+    x = [_Form(eye[i] * 2 ** Gr) for i in range(64)]
+    x[0].const = 2 ** (Gr + 2) + 2 ** (Gr + 10)
+    two_passes(x, inverse_line, bound_inv, (False, True))
+    fwd = max(p for p, is_fwd in peaks if is_fwd)
+    inv = max(p for p, is_fwd in peaks if not is_fwd)
+    return fwd, inv, len(peaks)
+
+
+@pytest.mark.parametrize("n,Fr,Gr", RECIPES)
+def test_compensation_headroom_every_recipe(oracle_mod, n, Fr, Gr):
+    fwd, inv, sites = _compensation_peaks(oracle_mod, n, Fr, Gr)
+    assert sites == 256   # 2 passes x 8 lines x 8 compensations, forward and inverse
+    assert fwd < 2 ** 30.5 and inv < 2 ** 29.6, (np.log2(fwd), np.log2(inv))
+
+
+def test_compensation_headroom_margin_is_under_one_bit(oracle_mod):
+    # for F = 16 the forward bound lies between 2^30 and 2^31: the pre-shift of one bit
+    # fits, a second would not, so the shift is k = 1 below M = 2^15 and no more
+    fwd, inv, _ = _compensation_peaks(oracle_mod, 10, 16, 12)
+    assert 2 ** 30 < fwd < 2 ** 31
+    fwd12, _, _ = _compensation_peaks(oracle_mod, 10, 12, 12)
+    assert abs(np.log2(fwd) - np.log2(fwd12) - 4) < 1e-6   # linear in 2^F
