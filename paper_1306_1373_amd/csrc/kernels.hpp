@@ -155,15 +155,25 @@ __device__ __forceinline__ void inverse_block(int (&x)[64]) {
 
 // Fused-codec quantizer for a coefficient c of a uint8 block in table slot s:
 // returns the dequantized value d 2^G and, through q_out, q itself.
+//
+// Every step but the truncation is a plain 32-bit instruction, which gfx950 can
+// pair: |c| by xor and subtract of the sign word; the float of m < 2^14 by
+// setting it into the mantissa of 2^23 and subtracting 2^23; the integer of
+// the dequantized q Q 2^G <= 2^23 (the clamp lemma: |q Q| <= 2048) by adding
+// 2^23 and subtracting the bits of 2^23.  Each of these is exact.
 template <int F>
 __device__ __forceinline__ int quant_dequant(int c, float rcp, float qscale, int32_t half, int &q_out) {
   constexpr int s = kQuantPreShift<F>;
-  const int a = max(c, -c) >> s;
-  const uint32_t m = static_cast<uint32_t>(a + half) >> (F + 3 - s);
-  const float qf = __builtin_truncf(static_cast<float>(m) * rcp);
-  const int d = static_cast<int>(static_cast<uint32_t>(qf * qscale));
+  constexpr uint32_t kTwo23Bits = 0x4B000000u;  // the bits of 2^23
+  constexpr float kTwo23 = 8388608.0f;
   const int sgn = c >> 31;
-  q_out = (static_cast<int>(static_cast<uint32_t>(qf)) ^ sgn) - sgn;
+  const int a = ((c ^ sgn) - sgn) >> s;
+  const uint32_t m = static_cast<uint32_t>(a + half) >> (F + 3 - s);
+  const float mf = __builtin_bit_cast(float, m | kTwo23Bits) - kTwo23;
+  const float qf = __builtin_truncf(mf * rcp);
+  const int d = static_cast<int>(__builtin_bit_cast(uint32_t, qf * qscale + kTwo23) - kTwo23Bits);
+  const int q = static_cast<int>(__builtin_bit_cast(uint32_t, qf + kTwo23) - kTwo23Bits);
+  q_out = (q ^ sgn) - sgn;
   return (d ^ sgn) - sgn;
 }
 
