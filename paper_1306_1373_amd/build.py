@@ -27,6 +27,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-shared",
     "-Wall", "-Wextra", "-Wno-unused-parameter",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results straight into VGPRs: no accumulator-register copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-fvisibility=hidden",
     f"-I{INCLUDE}", f"-I{CSRC}",
     "-Wl,-soname,libdctcodec.so",

@@ -120,16 +120,25 @@ struct FloatQuant {
   float rcp[15];  // 1/Q rounded to nearest
 };
 
-// q = sgn(F) floor(|F| / Q + 1/2); returns the dequantized q Q
+// q = sgn(F) floor(|F| / Q + 1/2); returns the dequantized q Q (the sign is put
+// on q first: the same value, one instruction fewer when the product is then
+// rounded to a 16-bit operand)
 __device__ __forceinline__ float fquant(float F, float Q, float rcp) {
   const float q = __builtin_floorf(__builtin_fabsf(F) * rcp + 0.5f);
-  return __builtin_copysignf(q * Q, F);
+  return __builtin_copysignf(q, F) * Q;
 }
 
 // clamp(floor(x + 128 + 1/2), 0, 255)
 __device__ __forceinline__ uint32_t freconstruct(float x) {
   const float p = __builtin_floorf(x + 128.5f);
   return static_cast<uint32_t>(__builtin_fminf(__builtin_fmaxf(p, 0.0f), 255.0f));
+}
+
+// The same into byte k of acc for the matrix form, given x + 128 + 1/2 (the
+// inverse product starts its accumulation there): the floor is an integer-valued
+// float, which the saturating byte conversion clamps exactly
+__device__ __forceinline__ uint32_t pack_reconstruct(float x_offset, uint32_t k, uint32_t acc) {
+  return __builtin_amdgcn_cvt_pk_u8_f32(__builtin_floorf(x_offset), k, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -272,6 +281,7 @@ struct MfmaTraits<true> {
 };
 
 inline constexpr int kMfmaWaves = 4;  // waves per workgroup; each wave codes 16 blocks per step
+inline constexpr int kKronDepth = 2;  // tiles whose words a wave has in flight ahead of the one it codes
 
 // Register-only layout of the matrix form.  With blocks as the N dimension,
 // the forward product is F^T = K X^T (M = coefficient, K = pixel) and the
@@ -358,28 +368,47 @@ __device__ __forceinline__ uint32_t words_sse(const uint32_t (&a)[4], const uint
   return pp - 2u * pr + rr;
 }
 
-// Per-lane constants of the matrix form: the A operands of both products and the
-// quantizer entries of the 16 coefficients the lane holds.
+// Per-lane constants of the matrix form: the A operands of the forward product
+// and the quantizer entries of the 16 coefficients the lane holds.  The A
+// operands of the inverse product live in LDS (InverseTable), which keeps the
+// kernel within four waves per SIMD.
 template <bool kBf16>
 struct KronConsts {
-  typename MfmaTraits<kBf16>::vec fa[4][2], ia[4][2];  // fa[t][s] = K[16t + i][sigma(s, g, e)], ia transposed
-  float qv[4][4], rq[4][4];                            // Q and 1/Q of coefficient 16t + 4g + r
+  typename MfmaTraits<kBf16>::vec fa[4][2];  // fa[t][s] = K[16t + i][sigma(s, g, e)]
+  float qv[4][4], rq[4][4];                  // Q and 1/Q of coefficient 16t + 4g + r
 };
 
+// The inverse product's A operands of every lane, ia[t][s][lane][e] =
+// K[sigma(s, g, e)][16t + i]: one 16-byte read per operand, consecutive lanes
+// at consecutive addresses.
+template <bool kBf16>
+struct InverseTable {
+  typename MfmaTraits<kBf16>::vec ia[4][2][64];
+};
+
+// Fills the lane's forward operands and quantizer entries, and (kCodec, wave 0)
+// the workgroup's inverse table; the caller synchronizes the workgroup after.
 template <bool kBf16, bool kCodec>
-__device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, const FloatQuant &fq, int i, int g) {
+__device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, InverseTable<kBf16> *inv, const FloatQuant &fq,
+                                           int wave, int i, int g) {
   using T = MfmaTraits<kBf16>;
   typedef typename T::elem elem;
   const uint16_t *K = T::table();
+  const int lane = 16 * g + i;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s) {
+      typename T::vec ia;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         kc.fa[t][s][e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
-        if constexpr (kCodec) kc.ia[t][s][e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
+        if constexpr (kCodec) ia[e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
       }
+      if constexpr (kCodec) {
+        if (wave == 0) inv->ia[t][s][lane] = ia;
+      }
+    }
   if constexpr (kCodec) {
     // coefficient 16t + 4g + r has u + v = 2t + r + g/2 + 4(g%2)
 #pragma unroll
@@ -406,13 +435,30 @@ __device__ __forceinline__ void kron_forward(const KronConsts<kBf16> &kc, const 
   typedef typename T::vec vec;
   typedef typename T::elem elem;
   vec bx[2];
+  if constexpr (!kBf16) {
+    // FP16 of b - 128 for two bytes at once: 0x6400 | b is 1024 + b, exact with
+    // 11 significant bits, and 1024 + b - 1152 is exact too
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 off = {static_cast<_Float16>(1152.0f), static_cast<_Float16>(1152.0f)};
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t word = w[2 * s + (e >> 2)];
-      bx[s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
-    }
+      for (int h = 0; h < 4; ++h) {
+        const uint32_t word = w[2 * s + (h >> 1)];
+        const uint32_t sel = (h & 1) ? 0x04030402u : 0x04010400u;  // bytes 2, 3 or 0, 1 under 0x64
+        const h2 v = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, word, sel)) - off;
+        bx[s][2 * h] = v[0];
+        bx[s][2 * h + 1] = v[1];
+      }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t word = w[2 * s + (e >> 2)];
+        bx[s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
+      }
+  }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     acc[t] = T::mma(kc.fa[t][0], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
@@ -422,7 +468,11 @@ __device__ __forceinline__ void kron_forward(const KronConsts<kBf16> &kc, const 
 
 // quantize, dequantize, inverse product and reconstruction: the four output words
 template <bool kBf16>
-__device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const f32x4 (&acc)[4], uint32_t (&rec)[4]) {
+__device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const InverseTable<kBf16> *inv, int lane,
+                                          const f32x4 (&acc)[4], uint32_t (&rec)[4]) {
+  // the table is read afresh at every call: an opaque index keeps the compiler
+  // from hoisting the reads out of the tile loop into registers
+  asm volatile("" : "+v"(lane));
   using T = MfmaTraits<kBf16>;
   typedef typename T::vec vec;
   typedef typename T::elem elem;
@@ -435,13 +485,38 @@ __device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const f32
       bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], kc.qv[t][r], kc.rq[t][r]));
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 x = T::mma(kc.ia[t][0], bq[0], f32x4{0.f, 0.f, 0.f, 0.f});
-    x = T::mma(kc.ia[t][1], bq[1], x);
+    f32x4 x = T::mma(inv->ia[t][0][lane], bq[0], f32x4{128.5f, 128.5f, 128.5f, 128.5f});
+    x = T::mma(inv->ia[t][1][lane], bq[1], x);
     uint32_t v = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v |= freconstruct(x[r]) << (8 * r);
+    for (int r = 0; r < 4; ++r) v = pack_reconstruct(x[r], r, v);
     rec[t] = v;
   }
+}
+
+// Position of block 16 tile + i.  tile is wave-uniform, so the division by bw is
+// one scalar division per tile; a lane then wraps at most once into the next
+// block row when the row holds at least 16 blocks (else each lane divides).
+__device__ __forceinline__ BlockPos tile_pos(int tile, int i, int W, int H, int bw, int nblocks) {
+  const int b0 = tile * 16;
+  int by, bx;
+  if (bw >= 16) {
+    const int by0 = b0 / bw;
+    bx = b0 - by0 * bw + i;
+    const bool wrap = bx >= bw;
+    bx = wrap ? bx - bw : bx;
+    by = by0 + (wrap ? 1 : 0);
+  } else {
+    by = (b0 + i) / bw;
+    bx = b0 + i - by * bw;
+  }
+  const bool live = b0 + i < nblocks;
+  BlockPos p;
+  p.live = live;
+  p.by = live ? by : 0;
+  p.bx = live ? bx : 0;
+  p.full = live && bx * 8 + 8 <= W && by * 8 + 8 <= H;
+  return p;
 }
 
 // kCodec = false: FP32 coefficients only; true: quantize, inverse, reconstruct, SSE.
@@ -451,21 +526,40 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
                                                               float *__restrict__ coef, FloatQuant fq,
                                                               uint8_t *__restrict__ dst, int dst_stride,
                                                               unsigned long long *__restrict__ sse) {
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  const int wave = wave_index(), l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  __shared__ InverseTable<kBf16> inv;
   KronConsts<kBf16> kc;
-  kron_setup<kBf16, kCodec>(kc, fq, i, g);
+  kron_setup<kBf16, kCodec>(kc, &inv, fq, wave, i, g);
+  if constexpr (kCodec) __syncthreads();
   uint64_t err = 0;
-  // each wave walks its tiles with the next tile's words already in flight
+  // each wave walks its tiles with the words of the next kKronDepth tiles in flight
   const int step = gridDim.x * kMfmaWaves;
   int tile = blockIdx.x * kMfmaWaves + wave;
-  BlockPos p = block_pos(tile * 16 + i, W, H, bw, nblocks);
-  uint32_t w[4] = {0u, 0u, 0u, 0u};
-  if (tile < ntiles && p.live) load_words(src, W, H, stride, p.by, p.bx, g, p.full, w);
+  uint32_t ring[kKronDepth][4];
+#pragma unroll
+  for (int d = 0; d < kKronDepth; ++d) {
+    const BlockPos pd = tile_pos(tile + d * step, i, W, H, bw, nblocks);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ring[d][k] = 0u;
+    if (tile + d * step < ntiles && pd.live) load_words(src, W, H, stride, pd.by, pd.bx, g, pd.full, ring[d]);
+  }
   for (; tile < ntiles; tile += step) {
     const int b = tile * 16 + i;
-    const BlockPos pn = block_pos(b + 16 * step, W, H, bw, nblocks);
-    uint32_t wn[4] = {0u, 0u, 0u, 0u};
-    if (tile + step < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, wn);
+    const BlockPos p = tile_pos(tile, i, W, H, bw, nblocks);
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = ring[0][k];
+#pragma unroll
+    for (int d = 0; d + 1 < kKronDepth; ++d)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ring[d][k] = ring[d + 1][k];
+    {
+      const int tn = tile + kKronDepth * step;
+      const BlockPos pn = tile_pos(tn, i, W, H, bw, nblocks);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ring[kKronDepth - 1][k] = 0u;
+      if (tn < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, ring[kKronDepth - 1]);
+    }
     f32x4 acc[4];
     kron_forward<kBf16>(kc, w, acc);
     if constexpr (!kCodec) {
@@ -477,17 +571,14 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
       }
     } else {
       uint32_t rec[4];
-      kron_code<kBf16>(kc, acc, rec);
+      kron_code<kBf16>(kc, &inv, l, acc, rec);
       if (p.live) {
         store_words(dst, W, H, dst_stride, p.by, p.bx, g, p.full, rec);
         err += words_sse(w, rec, W, H, p.by, p.bx, g, p.full);
       }
     }
-    p = pn;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = wn[k];
   }
-  if constexpr (kCodec) workgroup_add<64 * kMfmaWaves>(err, sse);
+  if constexpr (kCodec) workgroup_add<64 * kMfmaWaves>(err, sse, wave);
 }
 
 // JFIF YCbCr of one RGB pixel (integer, 2^-16 weights).  The luma weights sum to
@@ -564,12 +655,14 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
                                                                   uint8_t *__restrict__ out_cb,
                                                                   uint8_t *__restrict__ out_cr, int plane_stride,
                                                                   unsigned long long *__restrict__ sse) {
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  const int wave = wave_index(), l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  __shared__ InverseTable<kBf16> inv;
   KronConsts<kBf16> kc;
-  kron_setup<kBf16, true>(kc, fq, i, g);
+  kron_setup<kBf16, true>(kc, &inv, fq, wave, i, g);
+  __syncthreads();
   uint64_t err[3] = {0, 0, 0};
   for (int tile = blockIdx.x * kMfmaWaves + wave; tile < ntiles; tile += gridDim.x * kMfmaWaves) {
-    const BlockPos p = block_pos(tile * 16 + i, W, H, bw, nblocks);
+    const BlockPos p = tile_pos(tile, i, W, H, bw, nblocks);
     uint32_t w[3][4] = {};
     if (p.live) load_rgb_words(rgb, W, H, rgb_stride, p.by, p.bx, g, p.full, vec_ok, w[0], w[1], w[2]);
     uint8_t *outs[3] = {out_y, out_cb, out_cr};
@@ -578,7 +671,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
       f32x4 acc[4];
       kron_forward<kBf16>(kc, w[c], acc);
       uint32_t rec[4];
-      kron_code<kBf16>(kc, acc, rec);
+      kron_code<kBf16>(kc, &inv, l, acc, rec);
       if (p.live) {
         store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec);
         err[c] += words_sse(w[c], rec, W, H, p.by, p.bx, g, p.full);
@@ -587,7 +680,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    workgroup_add<64 * kMfmaWaves>(err[c], sse + c);
+    workgroup_add<64 * kMfmaWaves>(err[c], sse + c, wave);
     __syncthreads();
   }
 }
