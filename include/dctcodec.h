@@ -52,7 +52,7 @@
  *     library never aborts and never throws across this interface.
  *   - Thread safety: calls on different streams may run concurrently, except
  *     dct_psnr, which serialises on a library lock (it uses a per-device scratch
- *     word and waits for its stream).
+ *     word on the device and a pinned host copy of it, and waits for its stream).
  */
 #ifndef DCTCODEC_H
 #define DCTCODEC_H
@@ -288,8 +288,8 @@ DCT_API int dct_recipe_tables(int32_t *directions, int32_t *gains);
 /* Human-readable name of a dct_status value (static storage). */
 DCT_API const char *dct_status_string(int status);
 
-/* Releases the library's per-device scratch words.  Optional; later calls
- * allocate them again. */
+/* Releases the library's per-device scratch words (device and pinned host).
+ * Optional; later calls allocate them again. */
 DCT_API int dct_shutdown(void);
 
 #ifdef __cplusplus

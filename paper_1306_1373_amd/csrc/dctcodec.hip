@@ -28,6 +28,7 @@ constexpr int kMaxQs = 1024;
 
 std::mutex g_lock;                                   // guards the scratch table and dct_psnr
 std::array<unsigned long long *, kMaxDevices> g_scratch{};  // per device: {sse, max pixel}
+std::array<unsigned long long *, kMaxDevices> g_pinned{};   // per device: pinned host copy of the same
 std::array<int, kMaxDevices> g_arch_ok{};            // 0 unknown, 1 gfx950, -1 other
 
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
@@ -256,16 +257,25 @@ int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_str
     if (hipMalloc(&p, 2 * sizeof(unsigned long long)) != hipSuccess) return DCT_ERR_NOMEM;
     g_scratch[dev] = static_cast<unsigned long long *>(p);
   }
+  if (g_pinned[dev] == nullptr) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) return DCT_ERR_NOMEM;
+    g_pinned[dev] = static_cast<unsigned long long *>(p);
+  }
   unsigned long long *acc = g_scratch[dev];
+  unsigned long long *host = g_pinned[dev];
   hipStream_t s = as_stream(stream);
   dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 2);
   if (launched()) return DCT_ERR_DEVICE;
-  const int64_t items = static_cast<int64_t>((W + 7) / 8) * H;
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(items), 4096));
-  dct::sse_kernel<<<grid, dct::kWg, 0, s>>>(a, a_stride, b, b_stride, W, H, acc);
+  // grid.x covers a row's 8-byte segments, grid.y strides over rows: about 4096 workgroups
+  const int segs = (W + 7) / 8;
+  const unsigned gx = static_cast<unsigned>(std::min((segs + dct::kWg - 1) / dct::kWg, 16));
+  const unsigned gy = static_cast<unsigned>(std::max(1, std::min<int>(H, 4096 / static_cast<int>(gx))));
+  dct::sse_kernel<<<dim3(gx, gy), dct::kWg, 0, s>>>(a, a_stride, b, b_stride, W, H, acc);
   if (launched()) return DCT_ERR_DEVICE;
-  unsigned long long host[2] = {0, 0};
-  if (hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return DCT_ERR_DEVICE;
+  // the 16-byte result comes back through a pinned buffer: no staging copy
+  if (hipMemcpyAsync(host, acc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DCT_ERR_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return DCT_ERR_DEVICE;
   const uint64_t sse = host[0];
   const double mx = peak > 0.0 ? peak : static_cast<double>(static_cast<uint32_t>(host[1]));
@@ -597,6 +607,12 @@ int dct_shutdown(void) {
   for (auto &p : g_scratch) {
     if (p != nullptr) {
       if (hipFree(p) != hipSuccess) rc = DCT_ERR_DEVICE;
+      p = nullptr;
+    }
+  }
+  for (auto &p : g_pinned) {
+    if (p != nullptr) {
+      if (hipHostFree(p) != hipSuccess) rc = DCT_ERR_DEVICE;
       p = nullptr;
     }
   }

@@ -487,18 +487,18 @@ __global__ __launch_bounds__(kBlockThreads) DCT_FOUR_WAVES void codec_kernel(con
 }
 
 // a9 standalone: SSE of b against a (and the largest pixel of a) over W x H.
-// One thread per 8-pixel row segment, grid-stride.
+// One thread per 8-pixel row segment, strided over rows (grid.y) and segments
+// (grid.x).
 __global__ __launch_bounds__(kWg) void sse_kernel(const uint8_t *__restrict__ a, int a_stride,
                                                   const uint8_t *__restrict__ b, int b_stride, int W, int H,
                                                   unsigned long long *__restrict__ acc) {
   const int segs = (W + 7) / 8;
-  const int64_t total = static_cast<int64_t>(segs) * H;
   uint64_t sum = 0;
   uint32_t mx = 0;
-  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kWg + threadIdx.x; t < total;
-       t += static_cast<int64_t>(gridDim.x) * kWg) {
-    const int y = static_cast<int>(t / segs);
-    const int x0 = static_cast<int>(t - static_cast<int64_t>(y) * segs) * 8;
+  // rows across grid.y, the row's 8-byte segments across grid.x: 32-bit indices
+  for (int y = blockIdx.y; y < H; y += gridDim.y)
+  for (int sg = blockIdx.x * kWg + threadIdx.x; sg < segs; sg += gridDim.x * kWg) {
+    const int x0 = sg * 8;
     const uint8_t *ra = a + static_cast<size_t>(y) * a_stride + x0;
     const uint8_t *rb = b + static_cast<size_t>(y) * b_stride + x0;
     uint32_t a0, a1, b0, b1;
