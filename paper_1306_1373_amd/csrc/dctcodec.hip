@@ -27,7 +27,9 @@ constexpr int kMaxH = 1 << 24;  // a stack of images coded as one plane; the 2^3
 constexpr int kMaxQs = 1024;
 
 std::mutex g_lock;                                   // guards the scratch table and dct_psnr
-std::array<unsigned long long *, kMaxDevices> g_scratch{};  // per device: {sse, max pixel}
+// per device: {sse, max pixel}, then {sum, max} of each SSE workgroup
+constexpr int kSseMaxGroups = 1024;
+std::array<unsigned long long *, kMaxDevices> g_scratch{};
 std::array<unsigned long long *, kMaxDevices> g_pinned{};   // per device: pinned host copy of the same
 std::array<int, kMaxDevices> g_arch_ok{};            // 0 unknown, 1 gfx950, -1 other
 
@@ -254,7 +256,7 @@ int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_str
   std::lock_guard<std::mutex> guard(g_lock);
   if (g_scratch[dev] == nullptr) {
     void *p = nullptr;
-    if (hipMalloc(&p, 2 * sizeof(unsigned long long)) != hipSuccess) return DCT_ERR_NOMEM;
+    if (hipMalloc(&p, (2 + 2 * kSseMaxGroups) * sizeof(unsigned long long)) != hipSuccess) return DCT_ERR_NOMEM;
     g_scratch[dev] = static_cast<unsigned long long *>(p);
   }
   if (g_pinned[dev] == nullptr) {
@@ -265,13 +267,15 @@ int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_str
   unsigned long long *acc = g_scratch[dev];
   unsigned long long *host = g_pinned[dev];
   hipStream_t s = as_stream(stream);
-  dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 2);
-  if (launched()) return DCT_ERR_DEVICE;
-  // grid.x covers a row's 8-byte segments, grid.y strides over rows: about 4096 workgroups
+  // grid.x covers a row's 8-byte segments, grid.y strides over rows: at most
+  // kSseMaxGroups workgroups, each writing its own partial (every one is written)
   const int segs = (W + 7) / 8;
   const unsigned gx = static_cast<unsigned>(std::min((segs + dct::kWg - 1) / dct::kWg, 16));
-  const unsigned gy = static_cast<unsigned>(std::max(1, std::min<int>(H, 4096 / static_cast<int>(gx))));
-  dct::sse_kernel<<<dim3(gx, gy), dct::kWg, 0, s>>>(a, a_stride, b, b_stride, W, H, acc);
+  const unsigned gy = static_cast<unsigned>(std::max(1, std::min<int>(H, kSseMaxGroups / static_cast<int>(gx))));
+  unsigned long long *partial = acc + 2;
+  dct::sse_kernel<<<dim3(gx, gy), dct::kWg, 0, s>>>(a, a_stride, b, b_stride, W, H, partial);
+  if (launched()) return DCT_ERR_DEVICE;
+  dct::sse_reduce_kernel<<<1, dct::kWg, 0, s>>>(partial, static_cast<int>(gx * gy), acc);
   if (launched()) return DCT_ERR_DEVICE;
   // the 16-byte result comes back through a pinned buffer: no staging copy
   if (hipMemcpyAsync(host, acc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s) != hipSuccess)

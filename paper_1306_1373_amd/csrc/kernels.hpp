@@ -486,12 +486,14 @@ __global__ __launch_bounds__(kBlockThreads) DCT_FOUR_WAVES void codec_kernel(con
   workgroup_add<kBlockThreads>(err, sse, wave);
 }
 
-// a9 standalone: SSE of b against a (and the largest pixel of a) over W x H.
-// One thread per 8-pixel row segment, strided over rows (grid.y) and segments
-// (grid.x).
+// a9 standalone, first stage: SSE of b against a (and the largest pixel of a)
+// over W x H.  One thread per 8-pixel row segment, strided over rows (grid.y)
+// and segments (grid.x); workgroup w writes its sum and maximum to partial[2w]
+// and partial[2w + 1] (no atomics: one address shared by thousands of
+// workgroups serialises them).
 __global__ __launch_bounds__(kWg) void sse_kernel(const uint8_t *__restrict__ a, int a_stride,
                                                   const uint8_t *__restrict__ b, int b_stride, int W, int H,
-                                                  unsigned long long *__restrict__ acc) {
+                                                  unsigned long long *__restrict__ partial) {
   const int segs = (W + 7) / 8;
   uint64_t sum = 0;
   uint32_t mx = 0;
@@ -531,12 +533,57 @@ __global__ __launch_bounds__(kWg) void sse_kernel(const uint8_t *__restrict__ a,
 #pragma unroll
     for (int j = 0; j < 4; ++j) mx = max(mx, max((a0 >> (8 * j)) & 0xffu, (a1 >> (8 * j)) & 0xffu));
   }
-  workgroup_add<kWg>(sum, acc);
-  // largest pixel: reduce in the wave, one atomic per wave
+  __shared__ unsigned long long wsum[kWg / 64];
+  __shared__ uint32_t wmax[kWg / 64];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_xor(sum, off, 64);
     mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), off, 64)));
-  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int *>(acc + 1), mx);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wsum[threadIdx.x >> 6] = sum;
+    wmax[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < kWg / 64; ++w) {
+      t += wsum[w];
+      m = max(m, wmax[w]);
+    }
+    const unsigned wg = blockIdx.y * gridDim.x + blockIdx.x;
+    partial[2 * wg] = t;
+    partial[2 * wg + 1] = m;
+  }
+}
+
+// a9 standalone, second stage (one workgroup): acc[0] = the sum of the n
+// workgroups' sums, acc[1] = the largest of their maxima.
+__global__ __launch_bounds__(kWg) void sse_reduce_kernel(const unsigned long long *__restrict__ partial, int n,
+                                                         unsigned long long *__restrict__ acc) {
+  unsigned long long sum = 0;
+  unsigned long long mx = 0;
+  for (int w = threadIdx.x; w < n; w += kWg) {
+    sum += partial[2 * w];
+    mx = max(mx, partial[2 * w + 1]);
+  }
+  __shared__ unsigned long long ssum[kWg], smax[kWg];
+  ssum[threadIdx.x] = sum;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = kWg / 2; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) {
+      ssum[threadIdx.x] += ssum[threadIdx.x + h];
+      smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    acc[0] = ssum[0];
+    acc[1] = smax[0];
+  }
 }
 
 }  // namespace dct
