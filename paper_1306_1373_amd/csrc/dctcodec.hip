@@ -706,14 +706,14 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
   auto *g4 = reinterpret_cast<float *>(ws + L.g4);
   prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
-  layer1_kernel<<<px_grid(npix), kThreads, 0, s>>>(set, wq, a1, npix);
+  // layer 1 and layer 4: one thread per kRows vertically adjacent pixels of a column
+  const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
+  layer1_kernel<<<px_grid(ngroups), kThreads, 0, s>>>(set, wq, a1, ngroups);
   // tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image
   const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, a2, npix, ntiles);
   mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, a3, npix, ntiles);
-  // layer 4: one thread per kRows vertically adjacent pixels of a column
-  const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
   if (out != nullptr) {
     layer4_kernel<false><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, out, out_stride, nullptr,
                                                                nullptr, nullptr, 0.0f);

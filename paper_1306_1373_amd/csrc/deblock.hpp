@@ -101,27 +101,46 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(const float *__restrict_
   }
 }
 
+// pixel rows a thread (layers 1 and 4) or a wave's tile (layers 2 and 3) computes
+inline constexpr int kRows = 3;
+
 // a1 = relu(conv(x; W1, b1))
 __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const float *__restrict__ wq,
-                                                          _Float16 *__restrict__ a1, int64_t npix) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; p < npix;
-       p += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const Pix q = pix_of(s, p);
-    float x[9];
+                                                          _Float16 *__restrict__ a1, int64_t ngroups) {
+  // a thread computes kRows vertically adjacent pixels of one column: the
+  // (kRows + 2) x 3 neighbourhood is read and converted once for all of them
+  const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
+  for (int64_t gidx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; gidx < ngroups;
+       gidx += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const uint32_t u = static_cast<uint32_t>(gidx);
+    const uint32_t col_id = u / static_cast<uint32_t>(s.w);
+    const int c = static_cast<int>(u - col_id * static_cast<uint32_t>(s.w));
+    const int b = static_cast<int>(col_id / row_groups);
+    const int r0 = static_cast<int>(col_id - static_cast<uint32_t>(b) * row_groups) * kRows;
+    float x[kRows + 2][3];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) x[t] = plane_px(s, s.plane, q.b, q.r + t / 3 - 1, q.c + t % 3 - 1) * kInv255;
-    uint32_t words[kC / 2];
+    for (int k = 0; k < kRows + 2; ++k)
 #pragma unroll
-    for (int co = 0; co < kC; ++co) {
-      float acc = wq[kB1 + co];
+      for (int dx = 0; dx < 3; ++dx) x[k][dx] = plane_px(s, s.plane, b, r0 - 1 + k, c + dx - 1) * kInv255;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc += wq[kW1 + co * 9 + t] * x[t];
-      const uint32_t hbits = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc, 0.0f)));
-      words[co >> 1] = (co & 1) ? (words[co >> 1] | (hbits << 16)) : hbits;
+    for (int j = 0; j < kRows; ++j) {
+      const int r = r0 + j;
+      if (r >= s.h) break;
+      uint32_t words[kC / 2];
+#pragma unroll
+      for (int co = 0; co < kC; ++co) {
+        float acc = wq[kB1 + co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += wq[kW1 + co * 9 + t] * x[j + t / 3][t % 3];
+        const uint32_t hbits = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc, 0.0f)));
+        words[co >> 1] = (co & 1) ? (words[co >> 1] | (hbits << 16)) : hbits;
+      }
+      const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
+      uint4 *dst = reinterpret_cast<uint4 *>(a1 + p * kC);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        dst[k] = make_uint4(words[4 * k], words[4 * k + 1], words[4 * k + 2], words[4 * k + 3]);
     }
-    uint4 *dst = reinterpret_cast<uint4 *>(a1 + p * kC);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) dst[k] = make_uint4(words[4 * k], words[4 * k + 1], words[4 * k + 2], words[4 * k + 3]);
   }
 }
 
@@ -134,8 +153,6 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const floa
 // x 3 column offsets is loaded once and feeds every output row whose 3x3 window
 // covers it, so a tile needs (kRows + 2) * 3 / kRows loads instead of 9.  The
 // image, row and column of a tile are the same for the whole wave.
-inline constexpr int kRows = 3;
-
 __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float16 *__restrict__ ain,
                                                        const _Float16 *__restrict__ wh_layer,
                                                        const float *__restrict__ bias,
