@@ -141,6 +141,9 @@ const RecipeEntry *find_recipe(int n, int F, int G) {
 int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, const RecipeEntry &rc, int32_t qs,
                  uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
 
+// workgroups of a weight-gradient pass at most (each writes one partial row)
+constexpr int kGradGroups = 2048;
+
 struct DeblockLayout {
   size_t wq, wh, sq, a1, a2, a3, g4, ga, gb, part, bytes;
 };
@@ -681,9 +684,9 @@ DeblockLayout deblock_layout(int64_t npix, bool training) {
   if (training) o += gsz;
   L.gb = o;
   if (training) o += gsz;
-  // per-workgroup partial weight gradients: at most 1024 workgroups x the largest layer
+  // per-workgroup partial weight gradients: at most kGradGroups workgroups x the largest layer
   L.part = o;
-  if (training) o += align256(sizeof(float) * 1024 * (dct::db::kC * dct::db::kC * 9 + dct::db::kC));
+  if (training) o += align256(sizeof(float) * kGradGroups * (dct::db::kC * dct::db::kC * 9 + dct::db::kC));
   L.bytes = o;
   return L;
 }
@@ -739,12 +742,13 @@ int deblock_backward(const dct::db::ImageSet &set, int64_t npix, uint8_t *ws, co
   auto *ga = reinterpret_cast<float *>(ws + L.ga);
   auto *gb = reinterpret_cast<float *>(ws + L.gb);
   auto *part = reinterpret_cast<float *>(ws + L.part);
-  // at most 1024 workgroups per reduction, so the partials fit the workspace
-  const int per_wg = static_cast<int>(std::max<int64_t>(256, (npix + 1023) / 1024));
+  // at least 64 pixels and at most kGradGroups workgroups per weight-gradient
+  // pass, so the partials fit the workspace
+  const int per_wg = static_cast<int>(std::max<int64_t>(64, (npix + kGradGroups - 1) / kGradGroups));
   const int wg = static_cast<int>((npix + per_wg - 1) / per_wg);
   const unsigned pg = px_grid(npix);
   auto reduce = [&](int nw, int nb, float *dW, float *db) {
-    reduce_kernel<<<grid_for(nw + nb), kThreads, 0, s>>>(part, wg, nw, nb, dW, db);
+    reduce_kernel<<<static_cast<unsigned>((nw + nb + 63) / 64), kThreads, 0, s>>>(part, wg, nw, nb, dW, db);
   };
   // layer 4
   wgrad_kernel<kC, 1><<<wg, kThreads, 0, s>>>(set, g4, a3, part, npix, per_wg);

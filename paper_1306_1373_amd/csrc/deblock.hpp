@@ -433,17 +433,32 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(ImageSet s, const float
 }
 
 // Second stage: dW[k] = sum over workgroups of part[w][k] for the nw weights,
-// db[k] likewise for the nb biases stored after them.
+// db[k] likewise for the nb biases stored after them.  A workgroup reduces 64
+// consecutive entries; its four waves take every fourth partial row each (the
+// loads of a lane are independent, so many are in flight), then add their
+// four sums in LDS.
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restrict__ part, int nwg, int nw, int nb,
                                                           float *__restrict__ dW, float *__restrict__ db) {
-  const int k = blockIdx.x * kThreads + threadIdx.x;
-  if (k < nw + nb) {
-    float acc = 0.0f;
-    for (int w = 0; w < nwg; ++w) acc += part[static_cast<size_t>(w) * (nw + nb) + k];
+  constexpr int kWaves = kThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = nw + nb;
+  const int k = blockIdx.x * 64 + lane;
+  float acc = 0.0f;
+  if (k < n) {
+#pragma unroll 8
+    for (int w = wave; w < nwg; w += kWaves) acc += part[static_cast<size_t>(w) * n + k];
+  }
+  __shared__ float sums[kWaves][64];
+  sums[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && k < n) {
+    float t = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kWaves; ++j) t += sums[j][lane];
     if (k < nw)
-      dW[k] = acc;
+      dW[k] = t;
     else
-      db[k - nw] = acc;
+      db[k - nw] = t;
   }
 }
 
