@@ -225,6 +225,22 @@ def test_psnr_variants(hip, oracle_mod):
     assert si == 0 and math.isinf(pi)
 
 
+def test_psnr_grid_strides(hip, oracle_mod):
+    # a width of three workgroups of segments with a ragged last segment, and more
+    # rows than the grid has in y, so every stride of the SSE kernel is taken
+    rng = np.random.default_rng(29)
+    H, W = 1401, 5003
+    a = rng.integers(0, 251, (H, W), dtype=np.uint8)
+    b = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    a[H - 1, W - 1] = 253          # the largest pixel sits in the last, ragged segment
+    # pad bytes that would change both the SSE and the maximum if they were read
+    da, db = to_dev(a, 5008, fill=254), to_dev(b, 5016, fill=1)
+    p, s = hip.dct_psnr(da, db)
+    assert s == oracle_mod.sse(a, b) and p == oracle_mod.psnr(a, b)
+    p0, s0 = hip.dct_psnr(da, db, peak=0)
+    assert s0 == s and abs(p0 - oracle_mod.psnr(a, b, peak=0)) < 1e-12
+
+
 def test_determinism_and_streams(hip, oracle_mod, torch_mod):
     img = synth(640, 360, 9)
     src = to_dev(img)
