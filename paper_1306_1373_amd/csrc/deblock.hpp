@@ -184,6 +184,12 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
     for (int j = 0; j < kRows; ++j) acc[j][0] = acc[j][1] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < kRows + 2; ++k) {  // input row r0 - 1 + k
+      // one input row's loads in flight at a time (the accumulators pass through
+      // an empty asm, so no later row's loads are hoisted above this point): 128
+      // VGPRs and four waves per SIMD instead of 132 and three
+      static_assert(kRows == 3, "the fence names the three rows' accumulators");
+      asm volatile("" : "+v"(acc[0][0]), "+v"(acc[0][1]), "+v"(acc[1][0]), "+v"(acc[1][1]), "+v"(acc[2][0]),
+                   "+v"(acc[2][1]));
       const int rr = r0 - 1 + k;
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
