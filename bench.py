@@ -8,6 +8,11 @@ one 8192 x 8192 uint8 synthetic image, through dct_codec.  Five distinct
 images (seeds 0..4) rotate so that inputs plus outputs (640 MiB) exceed the
 256 MB Infinity Cache.  Inputs are resident in HBM before timing.  Prints one
 JSON line.
+
+Other workloads (--workload): staged (the four staged entry points, each stage
+against its roofline), precision (the floating-point forms on 256 RGB 2048 x 2048
+images), pareto (every built recipe), batch (10,000 images in one launch) and
+deblock (the learned deblocking filter: training, held-out gain, throughput).
 """
 import argparse
 import json
