@@ -111,6 +111,17 @@ DCT_API int dct_inverse(const int16_t *qcoef, int32_t qs, int32_t W, int32_t H, 
 DCT_API int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W,
              int32_t H, double peak, double *psnr_host, uint64_t *sse_host, void *stream);
 
+/* PSNR of eq. (23)-(24) (Sec. 4.1) from an exact sum of squared differences, as
+ * dct_psnr computes it: 20 log10(peak / sqrt(sse / npix)), +inf when sse = 0.
+ * For the SSE that dct_codec and the other fused entry points leave in device
+ * memory, once the caller has it on the host.
+ *   sse        the sum of squared differences over npix pixels.
+ *   npix       number of pixels, >= 1 (W H of the image).
+ *   peak       MAX of eq. (23), > 0 (255 for 8-bit planes).
+ *   psnr_host  host out.
+ * Host arithmetic only: enqueues nothing, touches no device. */
+DCT_API int dct_psnr_from_sse(uint64_t sse, int64_t npix, double peak, double *psnr_host);
+
 /* The whole codec in one pass, steps a1-a9: forward, quantize, dequantize,
  * inverse, reconstruct, and the SSE of the reconstruction against the source.
  * Bit-identical to dct_forward + dct_quantize + dct_inverse + dct_psnr.
@@ -261,6 +272,30 @@ DCT_API int dct_deblock_grad(const uint8_t *decoded, const uint8_t *original, in
                              size_t workspace_bytes, void *stream);
 DCT_API int dct_deblock_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
                              float beta1, float beta2, float eps, void *stream);
+
+/* Initial parameters of the deblocking network from a seed (params: float32
+ * device array [19105], overwritten): He-normal weights, N(0, 2 / (9 C_in)), for
+ * the three ReLU layers, zero biases, and a zero output layer, so that the
+ * untrained filter returns its input bit for bit.  The normal values come from
+ * the counter-based generator Philox4x32-10 (Salmon et al., SC 2011) with key
+ * (seed mod 2^32, seed >> 32) and counter (k, 0, 0, 0) for parameter k, through
+ * the Box-Muller transform of its first two words: u1 = (x0 + 1) 2^-32,
+ * u2 = x1 2^-32, z = sqrt(-2 ln u1) cos(2 pi u2).  The same seed gives the same
+ * parameters on every device. */
+DCT_API int dct_deblock_init(uint64_t seed, float *params, void *stream);
+
+/* The fallback rule of the learned filter: the trained filter is kept only if it
+ * raises the mean PSNR (eq. (23), Sec. 4.1) of a validation set over the plain
+ * decoded images.  sse_plain[k] and sse_filtered[k] (device, n uint64 each) are
+ * the SSEs of image k's decoded and filtered planes against its original; the
+ * gain of image k is 10 log10(sse_plain[k] / sse_filtered[k]) (its size and peak
+ * cancel; +inf when the filtered SSE is 0, 0 when both are).  If the mean gain
+ * is not above 0, the output layer of params (device) is zeroed, so that the
+ * filter returns the decoded image bit for bit.  mean_gain_host and kept_host
+ * (host, each may be NULL) get the mean gain in dB and 1 if the filter was kept.
+ * Waits for `stream` (it reads the SSEs back to the host). */
+DCT_API int dct_deblock_select(const uint64_t *sse_plain, const uint64_t *sse_filtered, int32_t n, float *params,
+                               double *mean_gain_host, int32_t *kept_host, void *stream);
 
 /* Three-channel images through the matrix-form codec in one pass: each pixel of
  * the interleaved RGB image is converted as dct_rgb_to_ycbcr does, each of the

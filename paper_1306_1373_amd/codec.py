@@ -69,6 +69,10 @@ _PROTOS = {
                                    C.c_void_p, C.c_size_t, C.c_void_p]),
     "dct_deblock_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                    C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "dct_deblock_init": (C.c_int, [C.c_uint64, C.c_void_p, C.c_void_p]),
+    "dct_deblock_select": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int32), C.c_void_p]),
+    "dct_psnr_from_sse": (C.c_int, [C.c_uint64, C.c_int64, C.c_double, C.POINTER(C.c_double)]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
@@ -369,18 +373,24 @@ class Deblocker:
     """The learned deblocking post-filter (dct_deblock_*): FP32 master parameters
     and Adam moments on the device, and workspaces sized on demand.  Crops are
     given as an int32 device tensor [n, 2] of top-left (row, col) positions in a
-    decoded plane (and the matching original plane) of the same pitch."""
+    decoded plane (and the matching original plane) of the same pitch.
 
-    def __init__(self, params=None, device="cuda"):
+    params: a host array of 19105 values, or None for the library's initial
+    parameters of `seed` (dct_deblock_init)."""
+
+    def __init__(self, params=None, device="cuda", seed: int = 0):
         import numpy as np
         import torch
         n = load().dct_deblock_nparam()
         if params is None:
-            params = init_deblock_params(0)
-        params = np.asarray(params, dtype=np.float32)
-        if params.size != n:
-            raise ValueError(f"expected {n} parameters")
-        self.params = torch.from_numpy(params.copy()).to(device)
+            self.params = torch.empty(n, dtype=torch.float32, device=device)
+            _check(load().dct_deblock_init(int(seed), self.params.data_ptr(), _stream(self.params)),
+                   "dct_deblock_init")
+        else:
+            params = np.asarray(params, dtype=np.float32)
+            if params.size != n:
+                raise ValueError(f"expected {n} parameters")
+            self.params = torch.from_numpy(params.copy()).to(device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.grad = torch.zeros_like(self.params)
@@ -449,18 +459,22 @@ class Deblocker:
         self.adam(lr)
         return self.loss
 
-
-def init_deblock_params(seed: int):
-    """Initial parameters: He-normal weights for the three ReLU layers, zero
-    biases, and a zero output layer, so the untrained filter is the identity."""
-    import numpy as np
-    rng = np.random.default_rng(seed)
-    parts = []
-    for co, ci in ((32, 1), (32, 32), (32, 32)):
-        parts.append(rng.normal(0.0, (2.0 / (9 * ci)) ** 0.5, co * ci * 9))
-        parts.append(np.zeros(co))
-    parts.append(np.zeros(32 * 9 + 1))
-    return np.concatenate(parts).astype(np.float32)
+    def select(self, sse_plain, sse_filtered):
+        """The fallback rule (dct_deblock_select): keep the trained filter only if
+        it raises the mean PSNR of a validation set, else zero its output layer.
+        sse_plain / sse_filtered: int64 device tensors of per-image SSEs of the
+        decoded and the filtered planes.  Returns (mean gain in dB, kept)."""
+        import torch
+        for t in (sse_plain, sse_filtered):
+            if t.dtype != torch.int64 or not t.is_contiguous() or not t.is_cuda:
+                raise TypeError("SSEs must be contiguous int64 device tensors")
+        if sse_plain.numel() != sse_filtered.numel():
+            raise ValueError("one SSE of each kind per image")
+        gain, kept = C.c_double(), C.c_int32()
+        _check(load().dct_deblock_select(sse_plain.data_ptr(), sse_filtered.data_ptr(), int(sse_plain.numel()),
+                                         self.params.data_ptr(), C.byref(gain), C.byref(kept),
+                                         _stream(self.params)), "dct_deblock_select")
+        return gain.value, bool(kept.value)
 
 
 def dct_codec_rgb_float(rgb, form, qs: int, planes=None, sse=None):
@@ -493,11 +507,10 @@ def dct_codec_rgb_float(rgb, form, qs: int, planes=None, sse=None):
 
 
 def psnr_from_sse(sse: int, W: int, H: int, peak: float = 255.0) -> float:
-    """Host arithmetic of eq. (23) for an SSE returned by dct_codec."""
-    import math
-    if sse == 0:
-        return math.inf
-    return 10.0 * math.log10(peak * peak * W * H / sse)
+    """PSNR (eq. (23)) of an SSE that dct_codec left in device memory (dct_psnr_from_sse)."""
+    out = C.c_double()
+    _check(load().dct_psnr_from_sse(int(sse), int(W) * int(H), float(peak), C.byref(out)), "dct_psnr_from_sse")
+    return out.value
 
 
 def recipe_info():

@@ -1,0 +1,272 @@
+// api_deblock.hip -- the learned deblocking post-filter of include/dctcodec.h:
+// inference, training gradient and Adam.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "dctcodec.h"
+#include "host.hpp"
+#include "deblock.hpp"
+
+namespace {
+
+using namespace dct::host;
+
+// workgroups of a weight-gradient pass at most (each writes one partial row)
+constexpr int kGradGroups = 2048;
+
+struct DeblockLayout {
+  size_t wq, wh, sq, a1, a2, a3, g4, ga, gb, part, bytes;
+};
+DeblockLayout deblock_layout(int64_t npix, bool training);
+int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *params, uint8_t *ws,
+                    const DeblockLayout &L, uint8_t *out, int out_stride, float *y, float *grad, double *loss,
+                    hipStream_t s);
+int deblock_backward(const dct::db::ImageSet &set, int64_t npix, uint8_t *ws, const DeblockLayout &L, float *grad,
+                     hipStream_t s);
+
+}  // namespace
+
+extern "C" {
+
+int32_t dct_deblock_nparam(void) { return dct::db::kNParam; }
+
+size_t dct_deblock_workspace_size(int64_t npix, int32_t training) {
+  if (npix < 1 || npix >= (int64_t{1} << 31)) return 0;
+  const DeblockLayout L = deblock_layout(npix, training != 0);
+  return L.bytes;
+}
+
+int dct_deblock_apply(const uint8_t *decoded, int32_t W, int32_t H, int32_t stride, const float *params,
+                      uint8_t *out, int32_t out_stride, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!plane_ok(decoded, W, H, stride) || !plane_ok(out, W, H, out_stride) || params == nullptr ||
+      !aligned(params, 4))
+    return DCT_ERR_INVALID;
+  const int64_t npix = static_cast<int64_t>(W) * H;
+  const DeblockLayout L = deblock_layout(npix, false);
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  dct::db::ImageSet set{decoded, nullptr, stride, W, H, nullptr, 1, H, W};
+  return deblock_forward(set, npix, params, static_cast<uint8_t *>(workspace), L, out, out_stride, nullptr,
+                         nullptr, nullptr, as_stream(stream));
+}
+
+int dct_deblock_forward(const uint8_t *decoded, int32_t plane_w, int32_t plane_h, int32_t stride, const int32_t *pos,
+                        int32_t n, int32_t h, int32_t w, const float *params, float *y, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+  if (!plane_ok(decoded, plane_w, plane_h, stride) || n < 1 || h < 1 || w < 1 || params == nullptr ||
+      y == nullptr || !aligned(y, 4) || (pos == nullptr && n != 1))
+    return DCT_ERR_INVALID;
+  const int64_t npix = static_cast<int64_t>(n) * h * w;
+  const DeblockLayout L = deblock_layout(npix, true);
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  dct::db::ImageSet set{decoded, decoded, stride, plane_w, plane_h, pos, n, h, w};
+  return deblock_forward(set, npix, params, static_cast<uint8_t *>(workspace), L, nullptr, 0, y, nullptr, nullptr,
+                         as_stream(stream));
+}
+
+int dct_deblock_grad(const uint8_t *decoded, const uint8_t *original, int32_t plane_w, int32_t plane_h,
+                     int32_t stride, const int32_t *pos, int32_t n, int32_t h, int32_t w, const float *params,
+                     float *grad, double *loss, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!plane_ok(decoded, plane_w, plane_h, stride) || !plane_ok(original, plane_w, plane_h, stride) || n < 1 ||
+      h < 1 || w < 1 || params == nullptr || grad == nullptr || !aligned(grad, 4) || loss == nullptr ||
+      !aligned(loss, 8) || (pos == nullptr && n != 1))
+    return DCT_ERR_INVALID;
+  const int64_t npix = static_cast<int64_t>(n) * h * w;
+  const DeblockLayout L = deblock_layout(npix, true);
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  dct::db::ImageSet set{decoded, original, stride, plane_w, plane_h, pos, n, h, w};
+  hipStream_t s = as_stream(stream);
+  auto *ws = static_cast<uint8_t *>(workspace);
+  int st = deblock_forward(set, npix, params, ws, L, nullptr, 0, nullptr, grad, loss, s);
+  if (st) return st;
+  return deblock_backward(set, npix, ws, L, grad, s);
+}
+
+int dct_deblock_init(uint64_t seed, float *params, void *stream) {
+  if (params == nullptr || !aligned(params, 4)) return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  dct::db::init_kernel<<<grid_for(dct::db::kNParam, dct::db::kThreads), dct::db::kThreads, 0, as_stream(stream)>>>(
+      params, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  return launched();
+}
+
+int dct_deblock_select(const uint64_t *sse_plain, const uint64_t *sse_filtered, int32_t n, float *params,
+                       double *mean_gain_host, int32_t *kept_host, void *stream) {
+  if (sse_plain == nullptr || sse_filtered == nullptr || n < 1 || n > (1 << 24) || params == nullptr ||
+      !aligned(params, 4) || !aligned(sse_plain, 8) || !aligned(sse_filtered, 8))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  hipStream_t s = as_stream(stream);
+  std::vector<uint64_t> host(2 * static_cast<size_t>(n));
+  if (hipMemcpyAsync(host.data(), sse_plain, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(host.data() + n, sse_filtered, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DCT_ERR_DEVICE;
+  // The PSNR gain of image k, eq. (23) of the filtered output minus that of the
+  // decoded one: the image's size and peak cancel, leaving 10 log10 of the ratio
+  // of the two SSEs (+inf when the filter makes the image exact, 0 when both are).
+  double sum = 0.0;
+  for (int32_t k = 0; k < n; ++k) {
+    const uint64_t a = host[k], b = host[n + k];
+    if (b == 0)
+      sum += a == 0 ? 0.0 : std::numeric_limits<double>::infinity();
+    else if (a == 0)
+      sum -= std::numeric_limits<double>::infinity();
+    else
+      sum += 10.0 * std::log10(static_cast<double>(a) / static_cast<double>(b));
+  }
+  const double mean = sum / n;  // NaN only if both infinities occur; then the filter is not kept
+  const bool keep = mean > 0.0;
+  if (!keep) {
+    dct::db::zero_output_layer_kernel<<<grid_for(dct::db::kNParam - dct::db::kW4, dct::db::kThreads),
+                                        dct::db::kThreads, 0, s>>>(params);
+    if (launched()) return DCT_ERR_DEVICE;
+  }
+  if (mean_gain_host) *mean_gain_host = mean;
+  if (kept_host) *kept_host = keep ? 1 : 0;
+  return DCT_OK;
+}
+
+int dct_deblock_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr, float beta1,
+                     float beta2, float eps, void *stream) {
+  if (params == nullptr || m == nullptr || v == nullptr || grad == nullptr || step < 1 || !(lr > 0.0f) ||
+      !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step));
+  const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step));
+  dct::db::adam_kernel<<<grid_for(dct::db::kNParam), dct::db::kThreads, 0, as_stream(stream)>>>(
+      params, m, v, grad, dct::db::kNParam, lr, beta1, beta2, eps, c1, c2);
+  return launched();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the deblocking network: FP16-rounded weights (FP32 and FP16), the
+// loss accumulator, three activation buffers (two for inference) and, for
+// training, dL/dy and two FP32 gradient buffers.  Every part 256-byte aligned.
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+DeblockLayout deblock_layout(int64_t npix, bool training) {
+  DeblockLayout L{};
+  size_t o = 0;
+  L.wq = o;
+  o += align256(sizeof(float) * dct::db::kNParam);
+  L.wh = o;
+  o += align256(sizeof(_Float16) * dct::db::kNParam);
+  L.sq = o;
+  o += 256;
+  const size_t act = align256(sizeof(_Float16) * dct::db::kC * static_cast<size_t>(npix));
+  L.a1 = o;
+  o += act;
+  L.a2 = o;
+  o += act;
+  L.a3 = training ? o : L.a1;  // inference writes the third activation over the first
+  if (training) o += act;
+  L.g4 = o;
+  if (training) o += align256(sizeof(float) * static_cast<size_t>(npix));
+  const size_t gsz = align256(sizeof(float) * dct::db::kC * static_cast<size_t>(npix));
+  L.ga = o;
+  if (training) o += gsz;
+  L.gb = o;
+  if (training) o += gsz;
+  // per-workgroup partial weight gradients: at most kGradGroups workgroups x the largest layer
+  L.part = o;
+  if (training) o += align256(sizeof(float) * kGradGroups * (dct::db::kC * dct::db::kC * 9 + dct::db::kC));
+  L.bytes = o;
+  return L;
+}
+
+unsigned px_grid(int64_t npix) {
+  return static_cast<unsigned>(std::min<int64_t>((npix + dct::db::kThreads - 1) / dct::db::kThreads, 1 << 16));
+}
+
+// Forward pass.  out != null: inference to the output plane.  Otherwise y (may be
+// null) gets y; with grad != null the loss terms and dL/dy are formed too.
+int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *params, uint8_t *ws,
+                    const DeblockLayout &L, uint8_t *out, int out_stride, float *y, float *grad, double *loss,
+                    hipStream_t s) {
+  using namespace dct::db;
+  auto *wq = reinterpret_cast<float *>(ws + L.wq);
+  auto *wh = reinterpret_cast<_Float16 *>(ws + L.wh);
+  auto *sq = reinterpret_cast<double *>(ws + L.sq);
+  auto *a1 = reinterpret_cast<_Float16 *>(ws + L.a1);
+  auto *a2 = reinterpret_cast<_Float16 *>(ws + L.a2);
+  auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
+  auto *g4 = reinterpret_cast<float *>(ws + L.g4);
+  prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
+  // layer 1 and layer 4: one thread per kRows vertically adjacent pixels of a column
+  const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
+  layer1_kernel<<<px_grid(ngroups), kThreads, 0, s>>>(set, wq, a1, ngroups);
+  // tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image
+  const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
+  const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
+  mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, a2, npix, ntiles);
+  mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, a3, npix, ntiles);
+  if (out != nullptr) {
+    layer4_kernel<false><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, out, out_stride, nullptr,
+                                                               nullptr, nullptr, 0.0f);
+    return launched();
+  }
+  zero_f32_kernel<<<1, kThreads, 0, s>>>(reinterpret_cast<float *>(sq), 2);
+  layer4_kernel<true><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, nullptr, 0, y, g4, sq,
+                                                            2.0f / static_cast<float>(npix));
+  if (grad != nullptr) mean_kernel<<<1, 64, 0, s>>>(sq, loss, 1.0 / static_cast<double>(npix));
+  return launched();
+}
+
+// Backward pass after deblock_forward with grad: writes the gradient of the mean
+// squared error with respect to all 19105 parameters into grad.
+int deblock_backward(const dct::db::ImageSet &set, int64_t npix, uint8_t *ws, const DeblockLayout &L, float *grad,
+                     hipStream_t s) {
+  using namespace dct::db;
+  auto *wq = reinterpret_cast<float *>(ws + L.wq);
+  auto *a1 = reinterpret_cast<_Float16 *>(ws + L.a1);
+  auto *a2 = reinterpret_cast<_Float16 *>(ws + L.a2);
+  auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
+  auto *g4 = reinterpret_cast<float *>(ws + L.g4);
+  auto *ga = reinterpret_cast<float *>(ws + L.ga);
+  auto *gb = reinterpret_cast<float *>(ws + L.gb);
+  auto *part = reinterpret_cast<float *>(ws + L.part);
+  // at least 64 pixels and at most kGradGroups workgroups per weight-gradient
+  // pass, so the partials fit the workspace
+  const int per_wg = static_cast<int>(std::max<int64_t>(64, (npix + kGradGroups - 1) / kGradGroups));
+  const int wg = static_cast<int>((npix + per_wg - 1) / per_wg);
+  const unsigned pg = px_grid(npix);
+  auto reduce = [&](int nw, int nb, float *dW, float *db) {
+    reduce_kernel<<<static_cast<unsigned>((nw + nb + 63) / 64), kThreads, 0, s>>>(part, wg, nw, nb, dW, db);
+  };
+  // layer 4
+  wgrad_kernel<kC, 1><<<wg, kThreads, 0, s>>>(set, g4, a3, part, npix, per_wg);
+  reduce(kC * 9, 1, grad + kW4, grad + kB4);
+  bwd4_kernel<<<pg, kThreads, 0, s>>>(set, g4, a3, wq, ga, npix);
+  // layer 3: ga = dL/d(pre-activation 3)
+  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, ga, a2, part, npix, per_wg);
+  reduce(kC * kC * 9, kC, grad + kW3, grad + kB3);
+  bwd_mid_kernel<<<pg, kThreads, 0, s>>>(set, ga, a2, wq + kW3, gb, npix);
+  // layer 2
+  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, gb, a1, part, npix, per_wg);
+  reduce(kC * kC * 9, kC, grad + kW2, grad + kB2);
+  bwd_mid_kernel<<<pg, kThreads, 0, s>>>(set, gb, a1, wq + kW2, ga, npix);
+  // layer 1
+  wgrad_kernel<1, kC><<<wg, kThreads, 0, s>>>(set, ga, nullptr, part, npix, per_wg);
+  reduce(kC * 9, kC, grad + kW1, grad + kB1);
+  return launched();
+}
+
+}  // namespace

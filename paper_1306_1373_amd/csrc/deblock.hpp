@@ -27,9 +27,11 @@
 //                      dL/dy (training)
 //   bwd4_kernel        dL/da3 through layer 4 and the ReLU of a3
 //   bwd_mid_kernel     dL/da through a 32 -> 32 layer and the ReLU of its input
-//   wgrad_kernel       weight and bias gradients of a layer: a reduction over
-//                      pixels per workgroup, then atomic adds
-//   adam_kernel        Adam with bias correction; refreshes the FP16 weights
+//   wgrad_kernel       weight and bias gradients of a layer, first stage: each
+//                      workgroup sums its pixels' products into a partial row
+//   reduce_kernel      second stage: adds the partial rows (no atomics)
+//   adam_kernel        Adam with bias correction
+//   init_kernel        the initial parameters from a seed (Philox4x32-10)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -492,6 +494,55 @@ __global__ __launch_bounds__(kThreads) void zero_f32_kernel(float *__restrict__ 
 
 __global__ void mean_kernel(const double *__restrict__ sq, double *__restrict__ loss, double inv_n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *loss = *sq * inv_n;
+}
+
+// Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and Shaw
+// ("Parallel random numbers: as easy as 1, 2, 3", SC 2011): ten rounds of two
+// 32 x 32 -> 64-bit products with the multipliers 0xD2511F53 and 0xCD9E8D57,
+// the key bumped by the Weyl constants 0x9E3779B9 and 0xBB67AE85 between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x, p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
+  }
+  return c;
+}
+
+// Initial parameters: He-normal weights N(0, 2 / (9 C_in)) for the three ReLU
+// layers, zero biases and a zero output layer, so that the untrained filter is
+// the identity.  Weight k draws counter (k, 0, 0, 0) under key (seed low word,
+// seed high word); the first two words give u1 = (x0 + 1) 2^-32 in (0, 1] and
+// u2 = x1 2^-32, and the Box-Muller transform sqrt(-2 ln u1) cos(2 pi u2) the
+// standard normal value (computed in double, stored as float).
+__global__ __launch_bounds__(kThreads) void init_kernel(float *__restrict__ p, uint32_t k0, uint32_t k1) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= kNParam) return;
+  double sd = 0.0;
+  if (k < kB1)
+    sd = 2.0 / 9.0;
+  else if ((k >= kW2 && k < kB2) || (k >= kW3 && k < kB3))
+    sd = 2.0 / (9.0 * kC);
+  float v = 0.0f;
+  if (sd > 0.0) {
+    const uint4 x = philox4x32_10(make_uint4(static_cast<uint32_t>(k), 0u, 0u, 0u), k0, k1);
+    const double u1 = (static_cast<double>(x.x) + 1.0) * 0x1p-32, u2 = static_cast<double>(x.y) * 0x1p-32;
+    const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+    v = static_cast<float>(sqrt(sd) * z);
+  }
+  p[k] = v;
+}
+
+// Zero the output layer (W4, b4) of a parameter array: the filter then returns
+// its input bit for bit.
+__global__ __launch_bounds__(kThreads) void zero_output_layer_kernel(float *__restrict__ p) {
+  const int k = kW4 + static_cast<int>(blockIdx.x * kThreads + threadIdx.x);
+  if (k < kNParam) p[k] = 0.0f;
 }
 
 }  // namespace db

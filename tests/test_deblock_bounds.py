@@ -1,0 +1,115 @@
+"""The per-entry error bounds of the deblocking network (deblock_bounds.py),
+checked on the CPU before the GPU tests rely on them:
+
+  * the exact gradient the bound is built around equals the oracle's
+    (oracle/deblock.c) to rounding;
+  * an emulation of the GPU's arithmetic (FP16 weights and activations, FP32
+    sums in BLAS order, backward signals rounded to FP16) stays inside the
+    bound on every entry, so the bound admits honest rounding;
+  * plausible kernel mistakes, applied to the exact gradient, break the bound
+    on many entries of the layer they touch, so a GPU gradient with such a
+    mistake cannot pass.
+"""
+import numpy as np
+import pytest
+
+import deblock_bounds as dbb
+
+
+@pytest.fixture(scope="module")
+def batch(oracle_mod):
+    from paper_1306_1373_amd.synth import synth_image
+    img = synth_image(96, 80, 4, 5.0)
+    rec, _ = oracle_mod.cordic_codec(img, 16)
+    pq = dbb.he_params(7).astype(np.float16).astype(np.float64)
+    rng = np.random.default_rng(8)
+    B, h = 8, 20
+    pos = np.stack([rng.integers(0, 80 - h, B), rng.integers(0, 96 - h, B)], 1)
+    x = np.stack([rec[r:r + h, c:c + h] for r, c in pos]).astype(np.float64) / 255.0
+    t = np.stack([img[r:r + h, c:c + h] for r, c in pos]).astype(np.float64) / 255.0
+    E = dbb.Exact(pq, x, t)
+    return pq, x, t, E, dbb.gradient_tolerance(E)
+
+
+SLICES = {"W1": slice(0, 288), "b1": slice(288, 320), "W2": slice(320, 9536), "b2": slice(9536, 9568),
+          "W3": slice(9568, 18784), "b3": slice(18784, 18816), "W4": slice(18816, 19104), "b4": slice(19104, 19105)}
+
+
+def test_exact_gradient_is_the_oracles(oracle_mod, batch):
+    pq, x, t, E, _ = batch
+    loss, g = oracle_mod.db_loss_grad(pq, x, t)
+    assert np.abs(E.grads() - g).max() <= 1e-12 * np.abs(g).max()
+    assert abs(loss - float(((E.y - E.t) ** 2).mean())) <= 1e-14
+
+
+def test_emulated_gpu_arithmetic_within_bound(batch):
+    pq, x, t, E, tol = batch
+    for g16 in (True, False):
+        y, g = dbb.emulate(pq, x, t, g16=g16)
+        ratio = np.abs(g - E.grads()) / tol
+        assert ratio.max() <= 1.0, (g16, ratio.max())
+        assert np.all(np.abs(y - E.y[0]) <= dbb.forward_tolerance(E))
+
+
+def _mutant(E, mut):
+    """The exact gradient with one plausible kernel mistake planted."""
+    g3 = E.g[3].copy()
+    if mut == "crop dropped":
+        g3[:, -1] = 0.0
+    g = [None, None, None, g3]
+    for l in (2, 1, 0):
+        w = E.L[l + 1][0]
+        if mut == "backward kernel not flipped" and l == 1:
+            w = w[:, :, ::-1, ::-1]
+        if mut == "backward taps transposed" and l == 2:
+            w = np.swapaxes(w, 2, 3)
+        G = dbb.conv_bwd_data(g[l + 1], w)
+        mask = E.z[l] > 0
+        if mut == "ReLU mask dropped" and l == 0:
+            mask = np.ones_like(mask)
+        if mut == "ReLU mask of the wrong layer" and l == 1:
+            mask = E.z[l + 1] > 0
+        g[l] = np.where(mask, G, 0.0)
+    out = []
+    for l in range(4):
+        gl, a = g[l], E.a[l]
+        if mut == "last row of each crop skipped" and l == 1:
+            gl = gl.copy()
+            gl[:, :, -1, :] = 0.0
+        if mut == "edges replicated, not zero" and l == 2:
+            ap = np.pad(a, ((0, 0), (0, 0), (1, 1), (1, 1)), mode="edge")
+            H, W = a.shape[2:]
+            dW = np.stack([np.stack([gl.reshape(gl.shape[0], -1) @
+                                     np.ascontiguousarray(ap[:, :, dy:dy + H, dx:dx + W]).reshape(a.shape[0], -1).T
+                                     for dx in range(3)], -1) for dy in range(3)], -2)
+        else:
+            dW = dbb.conv_bwd_weight(gl, a)
+        if mut == "weight taps transposed" and l == 1:
+            dW = np.swapaxes(dW, 2, 3)
+        if mut == "two input channels swapped" and l == 2:
+            dW[:, [3, 4]] = dW[:, [4, 3]]
+        out += [dW.ravel(), gl.sum(axis=(1, 2, 3))]
+    return np.concatenate(out)
+
+
+# mistake -> (parameter block it must show in, smallest share of that block's entries caught)
+MUTANTS = {
+    "weight taps transposed": ("W2", 0.25),
+    "two input channels swapped": ("W3", 0.03),
+    "backward kernel not flipped": ("W2", 0.25),
+    "backward taps transposed": ("W3", 0.25),
+    "ReLU mask dropped": ("W1", 0.25),
+    "ReLU mask of the wrong layer": ("W2", 0.25),
+    "edges replicated, not zero": ("W3", 0.2),
+    "last row of each crop skipped": ("W2", 0.05),
+    "crop dropped": ("W4", 0.25),
+}
+
+
+@pytest.mark.parametrize("mut", sorted(MUTANTS))
+def test_planted_mistakes_break_the_bound(batch, mut):
+    pq, x, t, E, tol = batch
+    block, share = MUTANTS[mut]
+    caught = np.abs(_mutant(E, mut) - E.grads()) > tol
+    got = caught[SLICES[block]].mean()
+    assert got >= share, (mut, block, got)
