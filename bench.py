@@ -574,7 +574,7 @@ def bench_deblock(args):
     t_codec0, t_codec1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # training on crops of the training images
-    db = codec.Deblocker(codec.init_deblock_params(1))
+    db = codec.Deblocker(seed=1)
     steps, B, C = args.train_steps, DB_BATCH, DB_CROP
     img = rng.integers(0, n_tr, (steps, B))
     pos = np.stack([img * S + rng.integers(0, S - C + 1, (steps, B)), rng.integers(0, S - C + 1, (steps, B))],
@@ -591,21 +591,25 @@ def bench_deblock(args):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - tt0
 
-    def gains(first, count, deblocker):
+    def filtered_sse(first, count, deblocker):
         out = codec.new_plane(S, S, dev)
-        g = []
+        sse = []
         for k in range(first, first + count):
             deblocker.apply(dec[k * S:(k + 1) * S], out=out)
-            _, s = codec.dct_psnr(orig[k * S:(k + 1) * S], out)
-            g.append(codec.psnr_from_sse(s, S, S) - codec.psnr_from_sse(int(sse_plain[k]), S, S))
-        return np.array(g)
+            sse.append(codec.dct_psnr(orig[k * S:(k + 1) * S], out)[1])
+        return torch.tensor(sse, dtype=torch.int64, device=dev)
 
-    valid_gain = float(gains(n_tr, n_va, db).mean())
-    accepted = valid_gain > 0.0
-    if not accepted:
-        p = db.params.cpu().numpy()
-        p[18816:] = 0.0
-        db = codec.Deblocker(p)
+    def gains(first, count, deblocker):
+        # PSNR gain per image: eq. (23) of the filtered plane minus that of the decoded one
+        f = filtered_sse(first, count, deblocker).cpu().numpy()
+        return np.array([codec.psnr_from_sse(int(f[i]), S, S) - codec.psnr_from_sse(int(sse_plain[first + i]), S, S)
+                         for i in range(count)])
+
+    # the fallback rule in the library: keep the filter only if it raises the
+    # validation set's mean PSNR, else zero its output layer
+    valid_sse = filtered_sse(n_tr, n_va, db)
+    plain_valid = torch.from_numpy(sse_plain[n_tr:n_tr + n_va].astype(np.int64)).to(dev)
+    valid_gain, accepted = db.select(plain_valid, valid_sse)
     test_gain = gains(n_tr + n_va, n_te, db)
 
     # inference throughput over the held-out images, and the codec's over the same images

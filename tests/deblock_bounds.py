@@ -14,6 +14,14 @@ dropped: an error of +-G whose sign is unrelated to that of any other such
 position, so it enters as variance G^2 and propagates like the rest.  The
 tolerance of a value is SIGMAS standard deviations.
 
+Errors are not independent where the computation repeats itself: two pixels
+whose inputs within the reach of a quantity are equal (a flat block, the zero
+fill past the edge of a plane) compute that quantity identically and carry the
+same error, which then adds coherently in a sum.  So pixels are grouped by
+their inputs within each quantity's reach, and every sum over taps or pixels
+multiplies a term's variance by the number of terms in its group (by Cauchy-
+Schwarz, (sum_k w_k e)^2 <= n sum_k w_k^2 e^2 for n terms sharing one error e).
+
 The convolutions here are plain linear algebra over arrays shaped
 (C, B, H, W): channels first, then images, rows, columns, with zero padding
 outside each image.  They serve only to propagate error variances and to build
@@ -55,8 +63,9 @@ def _pad(x):
     return np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)))
 
 
-def conv(x, w, b=None):
-    """y[co] = b[co] + sum_ci sum_{dy,dx} w[co, ci, dy, dx] x[ci][r + dy - 1, c + dx - 1]."""
+def conv(x, w, b=None, mult=None):
+    """y[co] = b[co] + sum_ci sum_{dy,dx} w[co, ci, dy, dx] x[ci][r + dy - 1, c + dx - 1]; with
+    mult (3, 3, B, H, W), tap (dy, dx) of output pixel p is weighted by mult[dy, dx][p]."""
     ci, B, H, W = x.shape
     co = w.shape[0]
     xp = _pad(x)
@@ -64,15 +73,17 @@ def conv(x, w, b=None):
     for dy in range(3):
         for dx in range(3):
             xs = np.ascontiguousarray(xp[:, :, dy:dy + H, dx:dx + W]).reshape(ci, -1)
-            y += np.ascontiguousarray(w[:, :, dy, dx]) @ xs
+            term = np.ascontiguousarray(w[:, :, dy, dx]) @ xs
+            y += term if mult is None else term * mult[dy, dx].reshape(1, -1)
     y = y.reshape(co, B, H, W)
     if b is not None:
         y += np.asarray(b, y.dtype)[:, None, None, None]
     return y
 
 
-def conv_bwd_data(g, w):
-    """The transpose of conv: gx[ci][r, c] = sum_co sum_{dy,dx} w[co, ci, dy, dx] g[co][r - dy + 1, c - dx + 1]."""
+def conv_bwd_data(g, w, mult=None):
+    """The transpose of conv: gx[ci][r, c] = sum_co sum_{dy,dx} w[co, ci, dy, dx] g[co][r - dy + 1, c - dx + 1];
+    with mult (3, 3, B, H, W), the term that reads neighbour (ny, nx) of pixel p is weighted by mult[ny, nx][p]."""
     co, B, H, W = g.shape
     ci = w.shape[1]
     gp = _pad(g)                       # gp[r + 1] = g[r]
@@ -80,7 +91,8 @@ def conv_bwd_data(g, w):
     for dy in range(3):
         for dx in range(3):
             gs = np.ascontiguousarray(gp[:, :, 2 - dy:2 - dy + H, 2 - dx:2 - dx + W]).reshape(co, -1)
-            out += np.ascontiguousarray(w[:, :, dy, dx].T) @ gs
+            term = np.ascontiguousarray(w[:, :, dy, dx].T) @ gs
+            out += term if mult is None else term * mult[2 - dy, 2 - dx].reshape(1, -1)
     return out.reshape(ci, B, H, W)
 
 
@@ -96,6 +108,46 @@ def conv_bwd_weight(g, x):
             xs = np.ascontiguousarray(xp[:, :, dy:dy + H, dx:dx + W]).reshape(ci, -1)
             out[:, :, dy, dx] = gf @ xs.T
     return out
+
+
+def pixel_classes(x, t, rx, rt):
+    """Class id (B, H, W) of every pixel: equal for pixels whose values of x within
+    Chebyshev radius rx and of t within radius rt agree, positions outside the
+    image counted as a value of their own.  Ids are 64-bit hashes of the
+    neighbourhood; a collision can only merge two classes (a larger group, a
+    larger bound)."""
+    B, H, W = x.shape
+    rng = np.random.default_rng(20240601)
+    h = np.zeros((B, H, W), np.uint64)
+    for img, r in ((x, rx), (t, rt)):
+        if img is None or r < 0:
+            continue
+        code = np.pad(np.rint(np.asarray(img) * 255.0).astype(np.int64) + 2, ((0, 0), (r, r), (r, r)),
+                      constant_values=1).astype(np.uint64)
+        for dy in range(2 * r + 1):
+            for dx in range(2 * r + 1):
+                m = np.uint64(rng.integers(1, 2 ** 63, dtype=np.int64)) * np.uint64(2) + np.uint64(1)
+                h = h * np.uint64(0x9E3779B97F4A7C15) + code[:, dy:dy + H, dx:dx + W] * m
+    return h
+
+
+def group_size(cls):
+    """Number of pixels of the batch in each pixel's class (B, H, W)."""
+    _, inv, cnt = np.unique(cls.ravel(), return_inverse=True, return_counts=True)
+    return cnt[inv].reshape(cls.shape).astype(np.float64)
+
+
+def neighbour_multiplicity(cls):
+    """mult[ny, nx][p] (3, 3, B, H, W): how many of pixel p's nine 3 x 3 neighbours
+    (positions outside the image excluded: they read exact zeros) share the class
+    of neighbour (ny - 1, nx - 1)."""
+    B, H, W = cls.shape
+    pad = np.pad(cls.astype(np.int64), ((0, 0), (1, 1), (1, 1)), constant_values=-1)
+    nb = [pad[:, dy:dy + H, dx:dx + W] for dy in range(3) for dx in range(3)]
+    mult = np.zeros((3, 3, B, H, W))
+    for i in range(9):
+        mult[i // 3, i % 3] = sum((nb[i] == nb[j]) for j in range(9))
+    return mult
 
 
 class Exact:
@@ -145,7 +197,9 @@ def forward_var(E):
     for l, (w, b) in enumerate(E.L):
         K = 9 * w.shape[1] + 1
         S = conv(np.abs(E.a[l]), np.abs(w)) + np.abs(b)[:, None, None, None]
-        v = conv(var_in, w * w) + K * (U32 * S) ** 2 / 3.0
+        # input a_l (a_0 = x) reaches l pixels of x: neighbours with equal inputs share their error
+        mult = neighbour_multiplicity(pixel_classes(E.x[0], None, l, -1))
+        v = conv(var_in, w * w, mult=mult) + K * (U32 * S) ** 2 / 3.0
         vz.append(v)
         if l < 3:
             var_in = np.where(E.z[l] > 0, v, 0.0) + (U16 * E.a[l + 1]) ** 2 / 3.0
@@ -171,24 +225,29 @@ def gradient_tolerance(E, g16=True, depth=None):
     var_t = 2.0 * (U32 * E.t) ** 2 / 3.0
     vg = [None] * 4                       # variance of the GPU's dL/dz_l
     vg[3] = E.s ** 2 * (var_y + var_t) + 3.0 * (U32 * E.g[3]) ** 2 / 3.0
+    # g[l] = dL/dz_{l+1} reaches 7 - l pixels of x and 3 - l of t
+    gcls = [pixel_classes(E.x[0], E.t[0], 7 - l, 3 - l) for l in range(4)]
     for l in (2, 1, 0):
         w = E.L[l + 1][0]
         K = 9 * w.shape[0]
         v_op = vg[l + 1] + ((U16 * E.g[l + 1]) ** 2 / 3.0 if g16 else 0.0)
         SG = conv_bwd_data(np.abs(E.g[l + 1]), np.abs(w))
-        vG = conv_bwd_data(v_op, w * w) + K * (U32 * SG) ** 2 / 3.0
+        vG = conv_bwd_data(v_op, w * w, mult=neighbour_multiplicity(gcls[l + 1])) + K * (U32 * SG) ** 2 / 3.0
         # ReLU decisions within reach of the pre-activation's rounding
         amb = np.abs(E.z[l]) <= SIGMAS * np.sqrt(vz[l]) + 2.0 ** -25
         vg[l] = np.where(E.z[l] > 0, vG, 0.0) + np.where(amb, E.G[l] ** 2 + vG, 0.0)
     out = []
     for l in range(4):
         a, va_l = E.a[l], va[l]
+        # a term g[l](p) a_l(p + offset) repeats wherever p's class of g[l] (whose
+        # reach covers a_l's at the neighbour) repeats
+        n = group_size(gcls[l])[None]
         v_op = vg[l] + ((U16 * E.g[l]) ** 2 / 3.0 if g16 else 0.0)
         SW = conv_bwd_weight(np.abs(E.g[l]), np.abs(a))
-        var_w = (conv_bwd_weight(v_op, a * a + va_l) + conv_bwd_weight(E.g[l] ** 2, va_l)
+        var_w = (conv_bwd_weight(n * v_op, a * a + va_l) + conv_bwd_weight(n * E.g[l] ** 2, va_l)
                  + depth * (U32 * SW) ** 2 / 3.0)
         Sb = np.abs(E.g[l]).sum(axis=(1, 2, 3))
-        var_b = v_op.sum(axis=(1, 2, 3)) + depth * (U32 * Sb) ** 2 / 3.0
+        var_b = (n * v_op).sum(axis=(1, 2, 3)) + depth * (U32 * Sb) ** 2 / 3.0
         out.append(SIGMAS * np.sqrt(var_w).ravel())
         out.append(SIGMAS * np.sqrt(var_b))
     return np.concatenate(out) + 1e-30

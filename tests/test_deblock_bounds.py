@@ -16,17 +16,30 @@ import pytest
 import deblock_bounds as dbb
 
 
-@pytest.fixture(scope="module")
-def batch(oracle_mod):
+def crops(plane, pos, h):
+    out = np.zeros((len(pos), h, h))
+    for k, (r, c) in enumerate(pos):
+        sub = plane[r:r + h, c:c + h]
+        out[k, :sub.shape[0], :sub.shape[1]] = sub
+    return out / 255.0
+
+
+@pytest.fixture(scope="module", params=["interior crops", "crop past the plane, flat blocks"])
+def batch(oracle_mod, request):
+    # the second batch repeats computations: its zero fill past the plane's edge
+    # and the flat blocks of a coarse quantizer give many pixels identical inputs,
+    # whose rounding errors add coherently
     from paper_1306_1373_amd.synth import synth_image
+    flat = request.param != "interior crops"
     img = synth_image(96, 80, 4, 5.0)
-    rec, _ = oracle_mod.cordic_codec(img, 16)
+    rec, _ = oracle_mod.cordic_codec(img, 64 if flat else 16)
     pq = dbb.he_params(7).astype(np.float16).astype(np.float64)
     rng = np.random.default_rng(8)
     B, h = 8, 20
     pos = np.stack([rng.integers(0, 80 - h, B), rng.integers(0, 96 - h, B)], 1)
-    x = np.stack([rec[r:r + h, c:c + h] for r, c in pos]).astype(np.float64) / 255.0
-    t = np.stack([img[r:r + h, c:c + h] for r, c in pos]).astype(np.float64) / 255.0
+    if flat:
+        pos[-1] = (70, 84)
+    x, t = crops(rec, pos, h), crops(img, pos, h)
     E = dbb.Exact(pq, x, t)
     return pq, x, t, E, dbb.gradient_tolerance(E)
 
