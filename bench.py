@@ -4,13 +4,16 @@
 
 A step is one pass of the whole path (level shift, row and column CORDIC
 Loeffler passes, quantize, dequantize, inverse passes, reconstruct, SSE) over
-one 8192 x 8192 uint8 synthetic image, through dct_codec.  Five distinct
+one 8192 x 8192 uint8 synthetic image, through dct_codec_accumulate into an SSE
+word zeroed before timing, so that each step is one codec kernel launch and
+HIP events on the launch stream time exactly those launches.  Five distinct
 images (seeds 0..4) rotate so that inputs plus outputs (640 MiB) exceed the
 256 MB Infinity Cache.  Inputs are resident in HBM before timing.  Prints one
 JSON line.
 
 Other workloads (--workload): staged (the four staged entry points, each stage
-against its roofline), precision (the floating-point forms on 256 RGB 2048 x 2048
+against its roofline), sweep (the paper's image sizes, GPU with and without
+host copies beside the oracle), precision (the floating-point forms on 256 RGB 2048 x 2048
 images), pareto (every built recipe), batch (10,000 images in one launch) and
 deblock (the learned deblocking filter: training, held-out gain, throughput).
 """
@@ -58,7 +61,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 64 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=("codec", "precision", "pareto", "batch", "deblock", "staged"),
+    ap.add_argument("--workload", choices=("codec", "precision", "pareto", "batch", "deblock", "staged",
+                                           "sweep"),
                     default="codec",
                     help="codec (default): the fused integer codec at 8192x8192; precision: "
                          "YCbCr + floating-point forms over 256 RGB 2048x2048 images; pareto: "
@@ -218,9 +222,43 @@ def profiled_traffic():
     return None
 
 
-def cpu_baseline(imgs, qs):
+def _median_time(fn, reps):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_legs(img, qs, cores):
+    """The oracle's other timings on bounded samples of one image (median of
+    `reps` runs each, about 15 s of wall time in all): the integer recipe codec on
+    one core, and the FP64 direct O(N^4) codec (the exact DCT of eq. (6)) on all
+    cores and on one core.  Values in Gpixel/s."""
+    import numpy as np
+
+    from oracle import bands
+    legs = {}
+    band = np.ascontiguousarray(img[:1024])                  # 8192 x 1024
+    small = np.ascontiguousarray(img[:1024, :1024])          # 1024 x 1024
+    for name, fn, px, reps, threads, what in (
+            ("recipe_one_core", lambda: bands.codec_bands(band, qs, threads=1), band.size, 5, 1,
+             f"recipe codec on the top {band.shape[0]} rows of image 0 ({band.shape[1]}x{band.shape[0]})"),
+            ("fp64_direct_all_cores", lambda: bands.exact_codec_bands(band, qs, threads=cores), band.size, 3,
+             cores, f"FP64 direct codec on the top {band.shape[0]} rows of image 0"),
+            ("fp64_direct_one_core", lambda: bands.exact_codec_bands(small, qs, threads=1), small.size, 3, 1,
+             f"FP64 direct codec on the top-left {small.shape[1]}x{small.shape[0]} of image 0")):
+        dt = _median_time(fn, reps)
+        legs[name] = {"value": round(px / dt / 1e9, 6), "unit": "Gpixel/s", "cores": threads,
+                      "sample": f"{what}, median of {reps}: {dt:.3f} s"}
+    return legs
+
+
+def cpu_baseline(imgs, qs, legs=True):
     """The oracle codec, band-parallel over the host cores, on every image of the
-    rotation (about 5 s of wall time on 16 cores); returns the image-0 result too."""
+    rotation (about 2 s of wall time on 16 cores), then the other legs of
+    cpu_legs; returns the image-0 result too."""
     from oracle import bands
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -232,9 +270,12 @@ def cpu_baseline(imgs, qs):
             first = (rec, sse)
     dt = time.perf_counter() - t0
     cpu = time.process_time() - c0
-    return {"value": len(imgs) * W * H / dt / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(imgs)} images of {W}x{H} (seeds 0-{len(imgs) - 1}), recipe codec, {cores} threads "
-                      f"over block-row bands: {dt:.2f} s wall, {cpu:.1f} s CPU"}, first[0], first[1]
+    out = {"value": len(imgs) * W * H / dt / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
+           "sample": f"{len(imgs)} images of {W}x{H} (seeds 0-{len(imgs) - 1}), recipe codec, {cores} threads "
+                     f"over block-row bands: {dt:.2f} s wall, {cpu:.1f} s CPU"}
+    if legs:
+        out["legs"] = cpu_legs(imgs[0], qs, cores)
+    return out, first[0], first[1]
 
 
 PREC_SIZE = 2048
@@ -669,6 +710,81 @@ def bench_deblock(args):
     print(json.dumps(out), flush=True)
 
 
+# The image sizes (W x H) of the paper's timing tables with its CPU and GPU times
+# in ms (a GTX 480 and an i3-2130; Sec. 4, Tables 1 and 2), quoted as context.
+PAPER_SIZES = [((3072, 3072), 1020.32, 8.92), ((2048, 2048), 266.23, 5.61), ((1600, 1400), 116.12, 2.20),
+               ((1024, 814), 88.23, 1.24), ((576, 720), 48.52, 0.82), ((512, 512), 16.42, 0.62),
+               ((200, 200), 6.88, 0.24), ((544, 512), 30.32, 0.58), ((512, 480), 26.84, 0.41),
+               ((448, 416), 21.22, 0.34), ((384, 352), 17.28, 0.26), ((320, 288), 10.86, 0.19)]
+
+
+def bench_sweep(args):
+    """The codec at the paper's image sizes: GPU time per image with the input in
+    HBM (HIP events around `reps` back-to-back calls), the same with the host
+    copies in (pinned upload, codec, download), and the oracle on one core and on
+    all cores (median of 3), each checked bit for bit; one JSON line."""
+    import numpy as np
+    import torch
+
+    from oracle import bands
+    from paper_1306_1373_amd import codec
+    from paper_1306_1373_amd.synth import synth_image
+
+    codec.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cores = len(os.sched_getaffinity(0))
+    rows = []
+    for k, ((w, h), cpu_ms, gpu_ms) in enumerate(PAPER_SIZES):
+        img = synth_image(w, h, 100 + k, 5.0)
+        src = codec.new_plane(w, h, dev)
+        src.copy_(torch.from_numpy(img).to(dev))
+        dst = codec.new_plane(w, h, dev)
+        reps = max(20, min(2000, int(2e9 // (w * h))))
+        sse = torch.zeros(reps + 10, dtype=torch.int64, device=dev)
+        for i in range(10):
+            codec.dct_codec_accumulate(src, QS, sse[i:i + 1], dst=dst)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(reps):
+            codec.dct_codec_accumulate(src, QS, sse[10 + i:11 + i], dst=dst)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        # with copies: pinned host buffers, upload + codec + download on one stream
+        hsrc = torch.from_numpy(img).pin_memory()
+        hdst = torch.empty((h, w), dtype=torch.uint8).pin_memory()
+        dense_src = torch.empty((h, w), dtype=torch.uint8, device=dev)
+        dense_dst = torch.empty((h, w), dtype=torch.uint8, device=dev)
+        one = torch.zeros(1, dtype=torch.int64, device=dev)
+        creps = max(10, reps // 10)
+        e0.record(stream)
+        for _ in range(creps):
+            dense_src.copy_(hsrc, non_blocking=True)
+            codec.dct_codec(dense_src, QS, dst=dense_dst, sse=one)
+            hdst.copy_(dense_dst, non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_copies = e0.elapsed_time(e1) / creps
+        rec, osse = bands.codec_bands(img, QS, threads=1)
+        parity = bool(np.array_equal(dst.cpu().numpy(), rec) and int(sse[10].item()) == osse
+                      and np.array_equal(hdst.numpy(), rec))
+        t1 = _median_time(lambda: bands.codec_bands(img, QS, threads=1), 3)
+        tn = _median_time(lambda: bands.codec_bands(img, QS, threads=cores), 3)
+        px = w * h
+        rows.append({"W": w, "H": h, "gpu_ms": round(ms, 5), "gpu_gpx_s": round(px / ms / 1e6, 3),
+                     "gpu_ms_with_copies": round(ms_copies, 5),
+                     "cpu_oracle_ms_1core": round(1e3 * t1, 3), f"cpu_oracle_ms_{cores}cores": round(1e3 * tn, 3),
+                     "psnr_db": round(codec.psnr_from_sse(osse, w, h), 6), "parity": parity,
+                     "paper_cpu_ms": cpu_ms, "paper_gpu_ms": gpu_ms})
+        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.1f} us ({px / ms / 1e6:.1f} Gpx/s), with copies "
+              f"{ms_copies * 1e3:.1f} us, oracle 1 core {t1 * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "sweep over the image sizes of the paper's timing tables "
+                                  "(synthetic images, seeds 100-111, sigma 5, qs 4)",
+                      "entry_point": "dct_codec_accumulate", "cores": cores, "rows": rows}), flush=True)
+
+
 def bench_staged(args):
     """The paper's stage split as separate launches: dct_forward (a1-a4), dct_quantize
     (a5), dct_inverse (a6-a8) and dct_psnr (a9) on the headline workload, each stage
@@ -802,6 +918,9 @@ def main():
     if args.workload == "staged":
         bench_staged(args)
         return
+    if args.workload == "sweep":
+        bench_sweep(args)
+        return
     import numpy as np
     import torch
 
@@ -821,26 +940,38 @@ def main():
         srcs.append(p)
         dsts.append(codec.new_plane(W, H, dev))
     total = args.warmup + args.steps
+    # one zeroed SSE word per step, filled before timing: each step is then exactly
+    # one codec_kernel launch (dct_codec_accumulate adds into its word)
     sse = torch.zeros(total, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()   # the stream the library launches on
 
     def step(k):
         i = k % N_IMAGES
-        codec.dct_codec(srcs[i], QS, dst=dsts[i], sse=sse[k:k + 1])
+        codec.dct_codec_accumulate(srcs[i], QS, sse[k:k + 1], dst=dsts[i])
 
     print(f"[bench] warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
+    start.record(stream)
     for k in range(args.warmup, total):
         step(k)
-    end.record()
+    end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
-    ms_per_step = ms / args.steps
+    ms_per_step = ms / args.steps   # average codec_kernel launch, back to back on one stream
     gpx = W * H / (ms_per_step * 1e-3) / 1e9
+    # the two-kernel entry point (a fill kernel zeroes the SSE word, then the codec
+    # kernel) timed the same way, for reference
+    sse2 = torch.zeros(args.steps, dtype=torch.int64, device=dev)
+    start.record(stream)
+    for k in range(args.steps):
+        codec.dct_codec(srcs[k % N_IMAGES], QS, dst=dsts[k % N_IMAGES], sse=sse2[k:k + 1])
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms_dct_codec = start.elapsed_time(end) / args.steps
 
     sse_h = sse.cpu().numpy()
     # every step of one image gives the same SSE (deterministic integer path)
@@ -869,7 +1000,8 @@ def main():
                                f"sigma 2-10), fused CORDIC-Loeffler codec, recipe n=10 F=12 G=12 P=15, "
                                f"qs={QS}",
                    "W": W, "H": H, "qs": QS, "images_rotated": N_IMAGES,
-                   "entry_point": "dct_codec"},
+                   "entry_point": "dct_codec_accumulate"},
+        "dct_codec_ms": round(ms_dct_codec, 5),
         "psnr_db_seed0": round(psnr0, 6),
         "hbm": {"achieved": round(BYTES_PER_PIXEL * gpx, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(BYTES_PER_PIXEL * gpx / HBM_PEAK_GBPS, 4),
@@ -878,12 +1010,14 @@ def main():
                      "peak": round(INT32_PEAK_TOPS, 2), "unit": "Tops/s",
                      "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": profiled_traffic(),
                      "kernel": "codec_kernel<Recipe<10, 12, 12>, false>", "ops_per_pixel": OPS_PER_PIXEL,
-                     "avg_kernel_ms": round(ms_per_step, 5)},
+                     "avg_kernel_ms": round(ms_per_step, 5),
+                     "timing": "HIP events on the launch stream around the timed steps, one kernel per step"},
         "deterministic": deterministic,
     }
     if not args.no_check or not args.no_cpu_baseline:
         print("[bench] oracle on image 0", file=sys.stderr, flush=True)
-        cb, rec, osse = cpu_baseline(host_imgs if not args.no_cpu_baseline else host_imgs[:1], QS)
+        cb, rec, osse = cpu_baseline(host_imgs if not args.no_cpu_baseline else host_imgs[:1], QS,
+                                     legs=not args.no_cpu_baseline)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in cb.items()}
         if not args.no_check:

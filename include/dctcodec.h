@@ -132,6 +132,18 @@ DCT_API int dct_psnr_from_sse(uint64_t sse, int64_t npix, double peak, double *p
 DCT_API int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
               int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream);
 
+/* dct_codec that adds the block SSEs to *sse_dev instead of overwriting it: one
+ * kernel launch and nothing else.  The caller zeroes *sse_dev once; calls on
+ * the bands or tiles of one image (each a plane of its own, block-aligned), on
+ * the frames of a sequence, or on the images of a set then leave the SSE of the
+ * whole in it, whose PSNR (eq. (23), Sec. 4.1) is over all their pixels
+ * (dct_psnr_from_sse with npix their total).  Calls that add into one word
+ * may overlap: the additions are atomic.  Arguments and every other output as
+ * dct_codec. */
+DCT_API int dct_codec_accumulate(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs,
+                                 uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev,
+                                 void *stream);
+
 /* Floating-point forms of the transform (the exact DCT of Sec. 2.5.1, eq. (6),
  * that Sec. 4.1 compares the Cordic-based codec against), for dct_forward_float
  * and dct_codec_float:

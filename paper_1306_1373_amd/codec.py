@@ -38,6 +38,8 @@ _PROTOS = {
                            C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_void_p]),
     "dct_codec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dct_codec_accumulate": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dct_forward_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_void_p, C.c_void_p]),
     "dct_codec_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -224,6 +226,12 @@ def dct_codec(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = F
     return _codec(src, qs, dst, qcoef, sse, want_qcoef, None)
 
 
+def dct_codec_accumulate(src, qs: int, sse, dst=None, qcoef=None, want_qcoef: bool = False):
+    """dct_codec that adds the SSE into ``sse`` (a one-element int64 device tensor the
+    caller has zeroed) instead of overwriting it; returns as dct_codec."""
+    return _codec(src, qs, dst, qcoef, sse, want_qcoef, "accumulate")
+
+
 def dct_codec_recipe(src, recipe, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
     """dct_codec under recipe (n, F, G); returns as dct_codec."""
     n, F, G = (int(v) for v in recipe)
@@ -249,6 +257,11 @@ def _codec(src, qs, dst, qcoef, sse, want_qcoef, recipe):
     if recipe is None:
         _check(load().dct_codec(p, W, H, s, int(qs), pd, ds, qptr, sse.data_ptr(), _stream(src)),
                "dct_codec")
+    elif recipe == "accumulate":
+        if sse.dtype != torch.int64 or sse.numel() < 1 or not sse.is_cuda:
+            raise TypeError("sse must be an int64 device tensor")
+        _check(load().dct_codec_accumulate(p, W, H, s, int(qs), pd, ds, qptr, sse.data_ptr(), _stream(src)),
+               "dct_codec_accumulate")
     else:
         _check(load().dct_codec_recipe(p, W, H, s, *recipe, int(qs), pd, ds, qptr, sse.data_ptr(),
                                        _stream(src)), "dct_codec_recipe")

@@ -45,8 +45,10 @@ const RecipeEntry *find_recipe(int n, int F, int G) {
   return found;
 }
 
+// zero_sse: overwrite *sse_dev (dct_codec) rather than add to it (dct_codec_accumulate)
 int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, const RecipeEntry &rc, int32_t qs,
-                 uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+                 uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream,
+                 bool zero_sse = true) {
   if (int st = check_device(nullptr)) return st;
   CodecArgs a{};
   a.src = src;
@@ -61,8 +63,10 @@ int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, c
   a.qcoef = qcoef_or_null;
   a.sse = reinterpret_cast<unsigned long long *>(sse_dev);
   hipStream_t s = as_stream(stream);
-  dct::fill_zero_kernel<<<1, 64, 0, s>>>(a.sse, 1);
-  if (launched()) return DCT_ERR_DEVICE;
+  if (zero_sse) {
+    dct::fill_zero_kernel<<<1, 64, 0, s>>>(a.sse, 1);
+    if (launched()) return DCT_ERR_DEVICE;
+  }
   rc.launch(a, s);
   return launched();
 }
@@ -83,6 +87,14 @@ int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int3
   const RecipeEntry *rc = nullptr;
   recipes_default(&rc);
   return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream);
+}
+
+int dct_codec_accumulate(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+                         int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+  if (!codec_args_ok(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev)) return DCT_ERR_INVALID;
+  const RecipeEntry *rc = nullptr;
+  recipes_default(&rc);
+  return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream, false);
 }
 
 int dct_codec_recipe(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t n_iter,

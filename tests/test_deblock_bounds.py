@@ -126,3 +126,17 @@ def test_planted_mistakes_break_the_bound(batch, mut):
     caught = np.abs(_mutant(E, mut) - E.grads()) > tol
     got = caught[SLICES[block]].mean()
     assert got >= share, (mut, block, got)
+
+
+def test_philox_reference_known_answers():
+    # the known-answer vectors published with the Random123 library for
+    # Philox4x32-10: zero counter and key, all-ones, and the digits of pi
+    from philox_ref import philox4x32_10
+    assert philox4x32_10([0, 0, 0, 0], (0, 0)) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert philox4x32_10([0xFFFFFFFF] * 4, (0xFFFFFFFF, 0xFFFFFFFF)) == [0x408F276D, 0x41C83B0E, 0xA20BC7C6,
+                                                                         0x6D5451FD]
+    assert philox4x32_10([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], (0xA4093822, 0x299F31D0)) == [
+        0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+    import numpy as np
+    # NumPy integer inputs give the same words (no 64-bit wrap in the products)
+    assert philox4x32_10([np.int64(27), 0, 0, 0], (np.int64(5), 0)) == philox4x32_10([27, 0, 0, 0], (5, 0))

@@ -253,6 +253,25 @@ def test_determinism_and_streams(hip, oracle_mod, torch_mod):
     assert torch_mod.equal(d1, d2) and torch_mod.equal(s1, s2) and torch_mod.equal(q1, q2)
 
 
+def test_accumulate_over_bands(hip, oracle_mod, torch_mod):
+    # dct_codec_accumulate over two block-aligned bands of one image (two planes
+    # that are views of one buffer): the reconstruction and the summed SSE equal
+    # the whole image's, and a second pass adds the same SSE again
+    W, H, cut = 1000, 620, 312
+    img = synth(W, H, 12)
+    src = to_dev(img)
+    rec, osse, oq = oracle_mod.cordic_codec(img, 6, want_q=True)
+    dst = hip.new_plane(W, H, "cuda")
+    sse = torch_mod.zeros(1, dtype=torch_mod.int64, device="cuda")
+    for rep in (1, 2):
+        _, _, q_top = hip.dct_codec_accumulate(src[:cut], 6, sse, dst=dst[:cut], want_qcoef=True)
+        _, _, q_bot = hip.dct_codec_accumulate(src[cut:], 6, sse, dst=dst[cut:], want_qcoef=True)
+        torch_mod.cuda.synchronize()
+        assert int(host(sse)[0]) == rep * osse
+        assert np.array_equal(host(dst), rec)
+        assert np.array_equal(np.concatenate([host(q_top), host(q_bot)]), oq)
+
+
 def test_invalid_arguments_raise(hip, torch_mod):
     src = to_dev(synth(16, 16, 1))
     with pytest.raises(hip.DctError) as e:
@@ -281,6 +300,15 @@ def test_full_size_8192(hip, oracle_mod):
     assert sse_h == osse
     assert np.array_equal(q_h, oq)
     assert np.array_equal(rec_h, orec)
+    say("[gpu] 8192x8192 fused codec, accumulating entry point (the benchmark's)")
+    import torch
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dst3 = hip.new_plane(8192, 8192, "cuda")
+    hip.dct_codec_accumulate(src, 4, acc, dst=dst3)
+    hip.dct_codec_accumulate(src, 4, acc, dst=dst3)
+    assert int(host(acc)[0]) == 2 * osse
+    assert np.array_equal(host(dst3), orec)
+    del dst3
     say("[gpu] 8192x8192 staged path")
     coef = hip.dct_forward(src)
     assert np.array_equal(host(coef), bands.forward_bands(img, threads=16))

@@ -23,6 +23,7 @@ import numpy as np
 import pytest
 
 import deblock_bounds as dbb
+from philox_ref import philox4x32_10
 
 
 def gpu_available() -> bool:
@@ -214,18 +215,6 @@ def test_apply_matches_oracle_1024(hip, oracle_mod):
     check_apply(hip, oracle_mod, dec, dbb.he_params(13), "1024 x 1024")
 
 
-def philox4x32_10(c, k):
-    """Philox4x32-10 (Salmon et al., SC 2011) on Python integers."""
-    M0, M1, W0, W1, MASK = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85, 0xFFFFFFFF
-    c, (k0, k1) = list(c), k
-    for r in range(10):
-        if r:
-            k0, k1 = (k0 + W0) & MASK, (k1 + W1) & MASK
-        p0, p1 = M0 * c[0], M1 * c[2]
-        c = [(p1 >> 32) ^ c[1] ^ k0, p1 & MASK, (p0 >> 32) ^ c[3] ^ k1, p0 & MASK]
-    return c
-
-
 def test_init_is_philox_box_muller(hip):
     seed = 0x1234_5678_9ABC_DEF0
     a = hip.Deblocker(seed=seed).params.cpu().numpy()
@@ -239,7 +228,7 @@ def test_init_is_philox_box_muller(hip):
     for k in sorted(set(rng.integers(0, 18784, 300)) | {0, 287, 320, 9535, 9568, 18783}):
         if 288 <= k < 320 or 9536 <= k < 9568:
             continue
-        x = philox4x32_10([k, 0, 0, 0], key)
+        x = philox4x32_10([int(k), 0, 0, 0], key)
         u1, u2 = (x[0] + 1.0) * 2.0 ** -32, x[1] * 2.0 ** -32
         sd = (2.0 / 9.0) ** 0.5 if k < 288 else (2.0 / 288.0) ** 0.5
         ref = np.float32(sd * np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2))
