@@ -122,6 +122,25 @@ DCT_API int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32
  * Host arithmetic only: enqueues nothing, touches no device. */
 DCT_API int dct_psnr_from_sse(uint64_t sse, int64_t npix, double peak, double *psnr_host);
 
+/* dct_psnr's SSE pass for callers that cannot allocate: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  It enqueues the
+ * same SSE kernels as dct_psnr (step a9, the sum of eq. (23)) but calls no
+ * allocating routine, does not wait, and leaves its result in device memory:
+ *   result_dev  out: two uint64 in device memory (8-byte aligned), overwritten
+ *               with {SSE of b against a over W x H, largest pixel of a}; the
+ *               PSNR then follows from dct_psnr_from_sse with npix = W H and
+ *               peak 255 (or the largest pixel, dct_psnr's peak = 0 reading).
+ * Its partial sums live in a fixed 16 KiB scratch array inside the library, one
+ * per device, resolved on the first call on each device and held until the
+ * process ends.  The grid never needs more than that array, so every plane
+ * the conventions above accept fits (the call still returns DCT_ERR_INVALID if
+ * a launch would need more).  Every workgroup overwrites its own partials, so
+ * nothing is cleared between calls.  Calls that overlap on one device (on
+ * different streams, or from different threads without ordering) share that
+ * array and race: serialise them. */
+DCT_API int dct_psnr_noalloc(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W,
+                             int32_t H, uint64_t *result_dev, void *stream);
+
 /* The whole codec in one pass, steps a1-a9: forward, quantize, dequantize,
  * inverse, reconstruct, and the SSE of the reconstruction against the source.
  * Bit-identical to dct_forward + dct_quantize + dct_inverse + dct_psnr.

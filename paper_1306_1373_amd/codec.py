@@ -75,6 +75,8 @@ _PROTOS = {
     "dct_deblock_select": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int32), C.c_void_p]),
     "dct_psnr_from_sse": (C.c_int, [C.c_uint64, C.c_int64, C.c_double, C.POINTER(C.c_double)]),
+    "dct_psnr_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_void_p, C.c_void_p]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
@@ -218,6 +220,23 @@ def dct_psnr(a, b, peak: float = 255.0):
     _check(load().dct_psnr(pa, sa, pb, sb, W, H, float(peak), C.byref(out), C.byref(sse),
                            _stream(a)), "dct_psnr")
     return out.value, int(sse.value)
+
+
+def dct_psnr_noalloc(a, b, result=None):
+    """Enqueue the SSE of plane b against plane a without any allocation in the
+    library; returns a two-element int64 device tensor {SSE, largest pixel of a}
+    (``result`` if given).  Does not wait for the stream."""
+    import torch
+    pa, W, H, sa = _plane(a, "a")
+    pb, W2, H2, sb = _plane(b, "b")
+    if (W, H) != (W2, H2):
+        raise ValueError("planes differ in shape")
+    if result is None:
+        result = torch.empty(2, dtype=torch.int64, device=a.device)
+    if result.dtype != torch.int64 or not result.is_contiguous() or result.numel() < 2:
+        raise TypeError("result must be a contiguous int64 tensor of two elements")
+    _check(load().dct_psnr_noalloc(pa, sa, pb, sb, W, H, result.data_ptr(), _stream(a)), "dct_psnr_noalloc")
+    return result
 
 
 def dct_codec(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):

@@ -73,6 +73,14 @@ constexpr int kSseMaxGroups = 1024;
 std::array<unsigned long long *, kMaxDevices> g_scratch{};  // guarded by lock()
 std::array<unsigned long long *, kMaxDevices> g_pinned{};   // per device: pinned host copy of the result
 
+// Scratch of dct_psnr_noalloc: the per-workgroup {sum, max} partials of the SSE
+// pass, 16 KiB, in the code object's own data (one copy per device, held until
+// the process ends).  Host code must not pass this name to a kernel: it is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress and is
+// kept per device in g_static_scratch.
+__device__ __align__(256) unsigned long long scratch[2 * kSseMaxGroups];
+std::array<unsigned long long *, kMaxDevices> g_static_scratch{};  // guarded by lock()
+
 dct::DequantTable dequant_table(int qs) {
   dct::DequantTable dq{};
   for (int s = 0; s < 15; ++s) dq.Q[s] = 1 + (1 + s) * qs;
@@ -161,6 +169,38 @@ int dct_psnr(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_str
   if (sse_host) *sse_host = sse;
   *psnr_host = psnr_of(sse, static_cast<double>(W) * static_cast<double>(H), mx);
   return DCT_OK;
+}
+
+int dct_psnr_noalloc(const uint8_t *a, int32_t a_stride, const uint8_t *b, int32_t b_stride, int32_t W, int32_t H,
+                     uint64_t *result_dev, void *stream) {
+  if (!plane_ok(a, W, H, a_stride) || !plane_ok(b, W, H, b_stride) || result_dev == nullptr ||
+      !aligned(result_dev, 8))
+    return DCT_ERR_INVALID;
+  int dev = 0;
+  if (int st = check_device(&dev)) return st;
+  unsigned long long *partial = nullptr;
+  {
+    std::lock_guard<std::mutex> guard(lock());
+    if (g_static_scratch[dev] == nullptr) {
+      // once per device, with that device current: the address of this device's copy
+      void *p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return DCT_ERR_DEVICE;
+      g_static_scratch[dev] = static_cast<unsigned long long *>(p);
+    }
+    partial = g_static_scratch[dev];
+  }
+  // the same grid as dct_psnr: at most kSseMaxGroups workgroups, each of which
+  // writes its own {sum, max} pair, so nothing in the scratch needs clearing
+  const int segs = (W + 7) / 8;
+  const unsigned gx = static_cast<unsigned>(std::min((segs + dct::kWg - 1) / dct::kWg, 16));
+  const unsigned gy = static_cast<unsigned>(std::max(1, std::min<int>(H, kSseMaxGroups / static_cast<int>(gx))));
+  if (gx * gy > static_cast<unsigned>(kSseMaxGroups)) return DCT_ERR_INVALID;  // beyond the scratch (never, by the grid rule)
+  hipStream_t s = as_stream(stream);
+  dct::sse_kernel<<<dim3(gx, gy), dct::kWg, 0, s>>>(a, a_stride, b, b_stride, W, H, partial);
+  if (launched()) return DCT_ERR_DEVICE;
+  dct::sse_reduce_kernel<<<1, dct::kWg, 0, s>>>(partial, static_cast<int>(gx * gy),
+                                                 reinterpret_cast<unsigned long long *>(result_dev));
+  return launched();
 }
 
 int dct_psnr_from_sse(uint64_t sse, int64_t npix, double peak, double *psnr_host) {
