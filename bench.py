@@ -62,7 +62,7 @@ def parse():
                     help="only run plain 64 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--workload", choices=("codec", "precision", "pareto", "batch", "deblock", "staged",
-                                           "sweep"),
+                                           "sweep", "mapping"),
                     default="codec",
                     help="codec (default): the fused integer codec at 8192x8192; precision: "
                          "YCbCr + floating-point forms over 256 RGB 2048x2048 images; pareto: "
@@ -77,6 +77,15 @@ def parse():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="no GPU work: condense the rocprofv3 outputs under DIR (subfolders trace, "
                          "fetch, write, copy_fetch, copy_write, sq) into the JSON given by --out")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="no GPU work: tabulate the rocprofv3 passes under DIR (one subfolder per pass; "
+                         "DIR/commands.txt lists the commands) for the kernels of --kernels into the "
+                         "markdown file --out")
+    ap.add_argument("--kernels", default="",
+                    help="for --summarize-counters: prefix=label pairs, comma-separated")
+    ap.add_argument("--pixels", type=float, default=0.0,
+                    help="for --summarize-counters: pixels each launch codes (per-pixel rows)")
+    ap.add_argument("--title", default="", help="for --summarize-counters: the table's heading")
     ap.add_argument("--kernel", default="void dct::codec_kernel<dct::Recipe<10, 12, 12>, false>",
                     help="kernel-name prefix for --summarize-profile")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "codec_kernel_8192.json"))
@@ -206,6 +215,80 @@ def profile_markdown(d, row):
                       f"{100 * sq.get('SQ_ACTIVE_INST_VALU2', 0) / sq['SQ_INSTS_VALU']:.1f}%: the share of VALU "
                       "issue cycles in which a SIMD issued two VALU instructions."]
     return "\n".join(lines) + "\n"
+
+
+def summarize_counters(root, kernels, pixels, title, out):
+    """Markdown table of rocprofv3 passes for several kernels side by side: the
+    kernel trace's average duration (a pass named trace), every counter's mean
+    per dispatch, HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
+    (passes copy_fetch / copy_write), and per-pixel figures."""
+    import csv
+    import glob
+    pairs = [kv.split("=", 1) for kv in kernels.split(",") if kv]
+    passes = sorted(d for d in os.listdir(root) if os.path.isdir(os.path.join(root, d)))
+    counters, trace = {}, {}
+    for ps in passes:
+        d = os.path.join(root, ps)
+        if ps == "trace":
+            stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))[0]
+            for r in csv.DictReader(open(stats)):
+                for pre, lab in pairs:
+                    if r["Name"].startswith(pre):
+                        trace[lab] = (float(r["AverageNs"]), int(r["Calls"]))
+            continue
+        if ps.startswith("copy_"):
+            continue
+        for pre, lab in pairs:
+            try:
+                for k, v in _counter_means(d, pre).items():
+                    counters.setdefault(k, {})[lab] = v
+            except (IndexError, KeyError):
+                pass
+    scale = {}
+    for ctr, ps in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
+        if os.path.isdir(os.path.join(root, ps)):
+            scale[ctr] = COPY_BYTES / 1024 / _counter_means(os.path.join(root, ps), "__amd_rocclr_copyBuffer")[ctr]
+    labs = [lab for _, lab in pairs]
+    lines = [f"# {title}", "", "Commands, run from `/tmp` with `TMPDIR=/tmp`, `R` the repository root:", "", "```"]
+    cmd_file = os.path.join(root, "commands.txt")
+    if os.path.exists(cmd_file):
+        lines += [c.rstrip() for c in open(cmd_file) if c.strip()]
+    lines += ["```", "", "| | " + " | ".join(f"`{lab}`" for lab in labs) + " |",
+              "|---|" + "---|" * len(labs)]
+    if trace:
+        lines.append("| kernel trace: average (launches) | " + " | ".join(
+            f"{trace[lab][0] / 1000:.1f} us ({trace[lab][1]})" if lab in trace else "" for lab in labs) + " |")
+    for ctr in sorted(counters):
+        lines.append(f"| {ctr} per dispatch | " + " | ".join(
+            f"{counters[ctr][lab]:.6g}" if lab in counters[ctr] else "" for lab in labs) + " |")
+    if pixels:
+        c = counters
+        for ctr, name in (("SQ_INSTS_VALU", "VALU instructions per pixel (x64 lanes)"),
+                          ("SQ_INSTS_LDS", "LDS instructions per pixel (x64 lanes)"),
+                          ("SQ_INSTS_SALU", "SALU instructions per pixel (x64 lanes)"),
+                          ("SQ_INSTS_VMEM", "vector memory instructions per pixel (x64 lanes)"),
+                          ("SQ_INSTS_MFMA", "MFMA instructions per 1024 pixels")):
+            if ctr in c:
+                f = 1024.0 if ctr == "SQ_INSTS_MFMA" else 64.0
+                lines.append(f"| {name} | " + " | ".join(
+                    f"{c[ctr][lab] * f / pixels:.2f}" if lab in c[ctr] else "" for lab in labs) + " |")
+        if "SQ_ACTIVE_INST_VALU2" in c and "SQ_INSTS_VALU" in c:
+            lines.append("| SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU | " + " | ".join(
+                f"{100 * c['SQ_ACTIVE_INST_VALU2'][lab] / c['SQ_INSTS_VALU'][lab]:.1f}%"
+                if lab in c["SQ_ACTIVE_INST_VALU2"] and lab in c["SQ_INSTS_VALU"] else "" for lab in labs) + " |")
+        if scale.keys() == {"FETCH_SIZE", "WRITE_SIZE"} and "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            tb = {lab: (c["FETCH_SIZE"][lab] * scale["FETCH_SIZE"] + c["WRITE_SIZE"][lab] * scale["WRITE_SIZE"]) * 1024
+                  for lab in labs if lab in c["FETCH_SIZE"] and lab in c["WRITE_SIZE"]}
+            lines.append(f"| HBM bytes per dispatch (copy scales x{scale['FETCH_SIZE']:.3f} fetch, "
+                         f"x{scale['WRITE_SIZE']:.3f} write) | " + " | ".join(
+                             f"{tb[lab] / 1e6:.1f} MB ({tb[lab] / pixels:.2f} B/px)" if lab in tb else ""
+                             for lab in labs) + " |")
+            if trace:
+                lines.append("| HBM GB/s (bytes / trace average) | " + " | ".join(
+                    f"{tb[lab] / trace[lab][0]:.0f}" if lab in tb and lab in trace else "" for lab in labs) + " |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def profiled_traffic():
@@ -720,9 +803,12 @@ PAPER_SIZES = [((3072, 3072), 1020.32, 8.92), ((2048, 2048), 266.23, 5.61), ((16
 
 def bench_sweep(args):
     """The codec at the paper's image sizes: GPU time per image with the input in
-    HBM (HIP events around `reps` back-to-back calls), the same with the host
-    copies in (pinned upload, codec, download), and the oracle on one core and on
-    all cores (median of 3), each checked bit for bit; one JSON line."""
+    HBM (HIP events around replays of a captured graph of `reps` codec launches,
+    so that the host's per-call cost does not count; every replay adds the SSE
+    once more to each launch's word, which is checked), the time of one eager call
+    from Python, the same with the host copies in (pinned upload, codec,
+    download), and the oracle on one core and on all cores (median of 3), each
+    checked bit for bit; one JSON line."""
     import numpy as np
     import torch
 
@@ -740,18 +826,36 @@ def bench_sweep(args):
         src = codec.new_plane(w, h, dev)
         src.copy_(torch.from_numpy(img).to(dev))
         dst = codec.new_plane(w, h, dev)
-        reps = max(20, min(2000, int(2e9 // (w * h))))
+        reps = max(20, min(200, int(2e9 // (w * h))))
+        replays = 5
         sse = torch.zeros(reps + 10, dtype=torch.int64, device=dev)
         for i in range(10):
             codec.dct_codec_accumulate(src, QS, sse[i:i + 1], dst=dst)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # one eager call at a time from Python: the host's cost per call included
         e0.record(stream)
         for i in range(reps):
-            codec.dct_codec_accumulate(src, QS, sse[10 + i:11 + i], dst=dst)
+            codec.dct_codec_accumulate(src, QS, sse[9:10], dst=dst)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms_eager = e0.elapsed_time(e1) / reps
+        graph = torch.cuda.CUDAGraph()
+        gstream = torch.cuda.Stream()
+        with torch.cuda.stream(gstream):
+            with torch.cuda.graph(graph, stream=gstream):
+                for i in range(reps):
+                    codec.dct_codec_accumulate(src, QS, sse[10 + i:11 + i], dst=dst)
+        torch.cuda.synchronize()
+        graph.replay()                      # warm
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(replays - 1):
+            graph.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / ((replays - 1) * reps)
+        graph_ok = bool((sse[10:10 + reps] == sse[10]).all().item())
         # with copies: pinned host buffers, upload + codec + download on one stream
         hsrc = torch.from_numpy(img).pin_memory()
         hdst = torch.empty((h, w), dtype=torch.uint8).pin_memory()
@@ -768,21 +872,64 @@ def bench_sweep(args):
         torch.cuda.synchronize()
         ms_copies = e0.elapsed_time(e1) / creps
         rec, osse = bands.codec_bands(img, QS, threads=1)
-        parity = bool(np.array_equal(dst.cpu().numpy(), rec) and int(sse[10].item()) == osse
-                      and np.array_equal(hdst.numpy(), rec))
+        parity = bool(np.array_equal(dst.cpu().numpy(), rec) and int(sse[10].item()) == replays * osse
+                      and graph_ok and np.array_equal(hdst.numpy(), rec))
         t1 = _median_time(lambda: bands.codec_bands(img, QS, threads=1), 3)
         tn = _median_time(lambda: bands.codec_bands(img, QS, threads=cores), 3)
         px = w * h
         rows.append({"W": w, "H": h, "gpu_ms": round(ms, 5), "gpu_gpx_s": round(px / ms / 1e6, 3),
-                     "gpu_ms_with_copies": round(ms_copies, 5),
+                     "gpu_ms_eager_call": round(ms_eager, 5), "gpu_ms_with_copies": round(ms_copies, 5),
                      "cpu_oracle_ms_1core": round(1e3 * t1, 3), f"cpu_oracle_ms_{cores}cores": round(1e3 * tn, 3),
                      "psnr_db": round(codec.psnr_from_sse(osse, w, h), 6), "parity": parity,
                      "paper_cpu_ms": cpu_ms, "paper_gpu_ms": gpu_ms})
-        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.1f} us ({px / ms / 1e6:.1f} Gpx/s), with copies "
+        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.2f} us in a graph ({px / ms / 1e6:.1f} Gpx/s), eager call "
+              f"{ms_eager * 1e3:.1f} us, with copies "
               f"{ms_copies * 1e3:.1f} us, oracle 1 core {t1 * 1e3:.1f} ms", file=sys.stderr, flush=True)
     print(json.dumps({"workload": "sweep over the image sizes of the paper's timing tables "
                                   "(synthetic images, seeds 100-111, sigma 5, qs 4)",
-                      "entry_point": "dct_codec_accumulate", "cores": cores, "rows": rows}), flush=True)
+                      "entry_point": "dct_codec_accumulate", "timing": "graph replay of back-to-back launches",
+                      "cores": cores, "rows": rows}), flush=True)
+
+
+def bench_mapping(args):
+    """The two thread mappings of the fused codec on the 8192 x 8192 rotation:
+    one lane per block (dct_codec) against one lane per block row with LDS
+    transposes (dct_codec_rows).  Each is timed with HIP events over --steps
+    calls (fill kernel included for both) and checked against the other."""
+    import torch
+
+    from paper_1306_1373_amd import codec
+    from paper_1306_1373_amd.synth import sigma_for_seed, synth_image
+
+    codec.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    srcs, dsts = [], []
+    for sd in range(N_IMAGES):
+        p = codec.new_plane(W, H, dev)
+        p.copy_(torch.from_numpy(synth_image(W, H, sd, sigma_for_seed(sd))).to(dev))
+        srcs.append(p)
+        dsts.append(codec.new_plane(W, H, dev))
+    out = {"workload": f"{W}x{H} rotation of {N_IMAGES} images, qs={QS}", "steps": args.steps}
+    ref = None
+    for name, fn in (("lane_per_block", codec.dct_codec), ("lane_per_row_lds", codec.dct_codec_rows)):
+        sse = torch.zeros(args.warmup + args.steps, dtype=torch.int64, device=dev)
+        for k in range(args.warmup):
+            fn(srcs[k % N_IMAGES], QS, dst=dsts[k % N_IMAGES], sse=sse[k:k + 1])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(args.warmup, args.warmup + args.steps):
+            fn(srcs[k % N_IMAGES], QS, dst=dsts[k % N_IMAGES], sse=sse[k:k + 1])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        got = (sse.cpu().numpy()[:N_IMAGES].tolist(), dsts[0].cpu())
+        same = None if ref is None else bool(got[0] == ref[0] and torch.equal(got[1], ref[1]))
+        ref = ref or got
+        out[name] = {"ms": round(ms, 5), "gpx_s": round(W * H / ms / 1e6, 2), "identical_to_lane_per_block": same}
+        print(f"[bench] {name}: {ms * 1e3:.1f} us, {W * H / ms / 1e6:.1f} Gpx/s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 def bench_staged(args):
@@ -903,6 +1050,9 @@ def main():
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.kernel, args.out)
         return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.kernels, args.pixels, args.title, args.out)
+        return
     if args.workload == "precision":
         bench_precision(args)
         return
@@ -920,6 +1070,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "mapping":
+        bench_mapping(args)
         return
     import numpy as np
     import torch

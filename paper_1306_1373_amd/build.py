@@ -22,7 +22,7 @@ SOURCES = [os.path.join(CSRC, f) for f in ("api_core.hip", "api_codec.hip", "rec
                                            "recipes_n8_n10.hip", "recipes_n12.hip", "api_float.hip",
                                            "api_batch.hip", "api_deblock.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp", "matrix_form.hpp",
-                                           "batch.hpp", "deblock.hpp", "staged.hpp", "host.hpp",
+                                           "batch.hpp", "deblock.hpp", "staged.hpp", "host.hpp", "rows.hpp",
                                            "codec_launch.hpp")] + [
     os.path.join(INCLUDE, "dctcodec.h")]
 

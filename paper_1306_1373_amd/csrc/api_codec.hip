@@ -2,11 +2,13 @@
 // a1-a9 in one pass) under the default recipe and under the built family.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "codec_launch.hpp"
 #include "dctcodec.h"
 #include "host.hpp"
+#include "rows.hpp"
 
 namespace dct {
 namespace host {
@@ -95,6 +97,29 @@ int dct_codec_accumulate(const uint8_t *src, int32_t W, int32_t H, int32_t src_s
   const RecipeEntry *rc = nullptr;
   recipes_default(&rc);
   return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream, false);
+}
+
+int dct_codec_rows(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+                   int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+  if (!codec_args_ok(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev)) return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  using RC = dct::DefaultRecipe;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  const int ngroups = (nblocks + 7) / 8;
+  const unsigned grid = static_cast<unsigned>(
+      std::min<int>((ngroups + 3) / 4, dct::rows::kMaxGroups));
+  auto *sse = reinterpret_cast<unsigned long long *>(sse_dev);
+  hipStream_t s = as_stream(stream);
+  dct::fill_zero_kernel<<<1, 64, 0, s>>>(sse, 1);
+  if (launched()) return DCT_ERR_DEVICE;
+  const dct::CodecQuant qa = codec_quant(qs, RC::frac, RC::inv_frac);
+  if (qcoef_or_null)
+    dct::rows::codec_rows_kernel<RC, true><<<grid, dct::rows::kThreads, 0, s>>>(
+        src, W, H, src_stride, bw, nblocks, qa, dst, dst_stride, qcoef_or_null, sse);
+  else
+    dct::rows::codec_rows_kernel<RC, false><<<grid, dct::rows::kThreads, 0, s>>>(
+        src, W, H, src_stride, bw, nblocks, qa, dst, dst_stride, nullptr, sse);
+  return launched();
 }
 
 int dct_codec_recipe(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t n_iter,

@@ -21,6 +21,12 @@ using namespace dct::host;
 
 // workgroups of a weight-gradient pass at most (each writes one partial row)
 constexpr int kGradGroups = 2048;
+// chunks (32 pixels of a row) per workgroup of the 32 -> 32 weight-gradient pass
+// and of the layer 1 / layer 4 passes
+constexpr int kMidChunks = 4;
+constexpr int kEdgeChunks = 16;
+// workgroups of the training output layer (each writes one partial loss sum)
+constexpr int kLossGroups = 1024;
 
 struct DeblockLayout {
   size_t wq, wh, sq, a1, a2, a3, g4, ga, gb, part, bytes;
@@ -158,8 +164,9 @@ int dct_deblock_adam(float *params, float *m, float *v, const float *grad, int32
 namespace {
 
 // Workspace of the deblocking network: FP16-rounded weights (FP32 and FP16), the
-// loss accumulator, three activation buffers (two for inference) and, for
-// training, dL/dy and two FP32 gradient buffers.  Every part 256-byte aligned.
+// loss partial sums, three activation buffers (two for inference) and, for
+// training, the scaled FP16 dL/dy, two scaled FP16 backward-signal buffers and
+// the partial weight-gradient rows.  Every part 256-byte aligned.
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 DeblockLayout deblock_layout(int64_t npix, bool training) {
@@ -170,7 +177,7 @@ DeblockLayout deblock_layout(int64_t npix, bool training) {
   L.wh = o;
   o += align256(sizeof(_Float16) * dct::db::kNParam);
   L.sq = o;
-  o += 256;
+  o += align256(sizeof(double) * kLossGroups);
   const size_t act = align256(sizeof(_Float16) * dct::db::kC * static_cast<size_t>(npix));
   L.a1 = o;
   o += act;
@@ -179,17 +186,24 @@ DeblockLayout deblock_layout(int64_t npix, bool training) {
   L.a3 = training ? o : L.a1;  // inference writes the third activation over the first
   if (training) o += act;
   L.g4 = o;
-  if (training) o += align256(sizeof(float) * static_cast<size_t>(npix));
-  const size_t gsz = align256(sizeof(float) * dct::db::kC * static_cast<size_t>(npix));
+  if (training) o += align256(sizeof(_Float16) * static_cast<size_t>(npix));
+  const size_t gsz = act;  // scaled FP16 backward signals, 32 channels
   L.ga = o;
   if (training) o += gsz;
   L.gb = o;
   if (training) o += gsz;
   // per-workgroup partial weight gradients: at most kGradGroups workgroups x the largest layer
   L.part = o;
-  if (training) o += align256(sizeof(float) * kGradGroups * (dct::db::kC * dct::db::kC * 9 + dct::db::kC));
+  if (training) o += align256(sizeof(float) * kGradGroups * dct::db::kNWMid);
   L.bytes = o;
   return L;
+}
+
+// S = 2^(floor(log2 npix) + 8), the scale of the FP16 backward signals
+float signal_scale(int64_t npix) {
+  int e = 0;
+  while ((int64_t{2} << e) <= npix) ++e;  // 2^e <= npix < 2^(e+1)
+  return std::ldexp(1.0f, e + 8);
 }
 
 unsigned px_grid(int64_t npix) {
@@ -208,7 +222,7 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   auto *a1 = reinterpret_cast<_Float16 *>(ws + L.a1);
   auto *a2 = reinterpret_cast<_Float16 *>(ws + L.a2);
   auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
-  auto *g4 = reinterpret_cast<float *>(ws + L.g4);
+  auto *g4 = reinterpret_cast<_Float16 *>(ws + L.g4);
   prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
   // layer 1 and layer 4: one thread per kRows vertically adjacent pixels of a column
   const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
@@ -216,17 +230,18 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   // tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image
   const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
-  mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, a2, npix, ntiles);
-  mid_kernel<<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, a3, npix, ntiles);
+  mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, nullptr, a2, npix, ntiles);
+  mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, nullptr, a3, npix, ntiles);
   if (out != nullptr) {
     layer4_kernel<false><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, out, out_stride, nullptr,
-                                                               nullptr, nullptr, 0.0f);
+                                                               nullptr, nullptr, 0.0f, 0.0f);
     return launched();
   }
-  zero_f32_kernel<<<1, kThreads, 0, s>>>(reinterpret_cast<float *>(sq), 2);
-  layer4_kernel<true><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, nullptr, 0, y, g4, sq,
-                                                            2.0f / static_cast<float>(npix));
-  if (grad != nullptr) mean_kernel<<<1, 64, 0, s>>>(sq, loss, 1.0 / static_cast<double>(npix));
+  const unsigned lgrid = static_cast<unsigned>(std::min<int64_t>((ngroups + kThreads - 1) / kThreads, kLossGroups));
+  layer4_kernel<true><<<lgrid, kThreads, 0, s>>>(set, a3, wq, ngroups, nullptr, 0, y, g4, sq,
+                                                 2.0f / static_cast<float>(npix), signal_scale(npix));
+  if (grad != nullptr) loss_reduce_kernel<<<1, kThreads, 0, s>>>(sq, static_cast<int>(lgrid), loss,
+                                                                 1.0 / static_cast<double>(npix));
   return launched();
 }
 
@@ -236,36 +251,44 @@ int deblock_backward(const dct::db::ImageSet &set, int64_t npix, uint8_t *ws, co
                      hipStream_t s) {
   using namespace dct::db;
   auto *wq = reinterpret_cast<float *>(ws + L.wq);
+  auto *wh = reinterpret_cast<_Float16 *>(ws + L.wh);
   auto *a1 = reinterpret_cast<_Float16 *>(ws + L.a1);
   auto *a2 = reinterpret_cast<_Float16 *>(ws + L.a2);
   auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
-  auto *g4 = reinterpret_cast<float *>(ws + L.g4);
-  auto *ga = reinterpret_cast<float *>(ws + L.ga);
-  auto *gb = reinterpret_cast<float *>(ws + L.gb);
+  auto *g4 = reinterpret_cast<_Float16 *>(ws + L.g4);
+  auto *ga = reinterpret_cast<_Float16 *>(ws + L.ga);
+  auto *gb = reinterpret_cast<_Float16 *>(ws + L.gb);
   auto *part = reinterpret_cast<float *>(ws + L.part);
-  // at least 64 pixels and at most kGradGroups workgroups per weight-gradient
-  // pass, so the partials fit the workspace
-  const int per_wg = static_cast<int>(std::max<int64_t>(64, (npix + kGradGroups - 1) / kGradGroups));
-  const int wg = static_cast<int>((npix + per_wg - 1) / per_wg);
-  const unsigned pg = px_grid(npix);
-  auto reduce = [&](int nw, int nb, float *dW, float *db) {
-    reduce_kernel<<<static_cast<unsigned>((nw + nb + 63) / 64), kThreads, 0, s>>>(part, wg, nw, nb, dW, db);
+  const float inv_s = 1.0f / signal_scale(npix);  // exact: a power of two
+  // chunks of 32 pixels of one image row; each pass's workgroups take a fixed
+  // number of them, at most kGradGroups workgroups (the partial rows' room)
+  const uint32_t nchunks = static_cast<uint32_t>(static_cast<int64_t>(set.n) * set.h * ((set.w + 31) / 32));
+  auto per_group = [&](uint32_t want) {
+    return std::max<uint32_t>(want, (nchunks + kGradGroups - 1) / kGradGroups);
   };
+  const uint32_t cpw_mid = per_group(kMidChunks), cpw_edge = per_group(kEdgeChunks);
+  const unsigned wg_mid = (nchunks + cpw_mid - 1) / cpw_mid, wg_edge = (nchunks + cpw_edge - 1) / cpw_edge;
+  auto reduce = [&](unsigned nwg, int nw, int nb, float *dW, float *db, float wscale) {
+    reduce_kernel<<<static_cast<unsigned>((nw + nb + 63) / 64), kThreads, 0, s>>>(part, static_cast<int>(nwg), nw,
+                                                                                   nb, dW, db, wscale, inv_s);
+  };
+  const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
+  const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   // layer 4
-  wgrad_kernel<kC, 1><<<wg, kThreads, 0, s>>>(set, g4, a3, part, npix, per_wg);
-  reduce(kC * 9, 1, grad + kW4, grad + kB4);
-  bwd4_kernel<<<pg, kThreads, 0, s>>>(set, g4, a3, wq, ga, npix);
-  // layer 3: ga = dL/d(pre-activation 3)
-  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, ga, a2, part, npix, per_wg);
-  reduce(kC * kC * 9, kC, grad + kW3, grad + kB3);
-  bwd_mid_kernel<<<pg, kThreads, 0, s>>>(set, ga, a2, wq + kW3, gb, npix);
+  wgrad_edge_kernel<false><<<wg_edge, 64, 0, s>>>(set, a3, g4, part, nchunks, cpw_edge);
+  reduce(wg_edge, kC * 9, 1, grad + kW4, grad + kB4, inv_s);
+  bwd4_kernel<<<px_grid(npix), kThreads, 0, s>>>(set, g4, a3, wq, ga, npix);
+  // layer 3: ga = S dL/d(pre-activation 3)
+  wgrad_mid_kernel<<<wg_mid, 192, 0, s>>>(set, ga, a2, part, nchunks, cpw_mid);
+  reduce(wg_mid, kC * kC * 9, kC, grad + kW3, grad + kB3, inv_s);
+  mid_kernel<true><<<mgrid, kThreads, 0, s>>>(set, ga, wh + kW3, nullptr, a2, gb, npix, ntiles);
   // layer 2
-  wgrad_kernel<kC, kC><<<wg, kThreads, 0, s>>>(set, gb, a1, part, npix, per_wg);
-  reduce(kC * kC * 9, kC, grad + kW2, grad + kB2);
-  bwd_mid_kernel<<<pg, kThreads, 0, s>>>(set, gb, a1, wq + kW2, ga, npix);
-  // layer 1
-  wgrad_kernel<1, kC><<<wg, kThreads, 0, s>>>(set, ga, nullptr, part, npix, per_wg);
-  reduce(kC * 9, kC, grad + kW1, grad + kB1);
+  wgrad_mid_kernel<<<wg_mid, 192, 0, s>>>(set, gb, a1, part, nchunks, cpw_mid);
+  reduce(wg_mid, kC * kC * 9, kC, grad + kW2, grad + kB2, inv_s);
+  mid_kernel<true><<<mgrid, kThreads, 0, s>>>(set, gb, wh + kW2, nullptr, a1, ga, npix, ntiles);
+  // layer 1: the pixel values' 1/255 joins the scale of the weight gradients
+  wgrad_edge_kernel<true><<<wg_edge, 64, 0, s>>>(set, ga, nullptr, part, nchunks, cpw_edge);
+  reduce(wg_edge, kC * 9, kC, grad + kW1, grad + kB1, inv_s * kInv255);
   return launched();
 }
 

@@ -11,25 +11,42 @@
 // accumulation is FP32; gradients are FP32.
 //
 // Data layout: activations are pixel-major with the 32 channels of a pixel in
-// 64 contiguous bytes (FP16) or 128 bytes (FP32 gradients).  Pixels are numbered
-// image by image, row-major.  An "image set" is n images of h x w whose top-left
-// corners sit at given (row, col) positions of one uint8 plane (training crops),
-// or one image at the origin (inference).
+// 64 contiguous bytes (FP16).  Pixels are numbered image by image, row-major.
+// An "image set" is n images of h x w whose top-left corners sit at given
+// (row, col) positions of one uint8 plane (training crops), or one image at the
+// origin (inference).
+//
+// Backward signals.  The training pass keeps g_l = dL/dz_l (z_l the layer's
+// pre-activation) as FP16 values times an exact power of two S (kept in the
+// same pixel-major layout), so that every product of the backward pass runs on
+// the matrix cores with FP16 operands and FP32 sums.  S = 2^(floor(log2 N) + 8)
+// for N pixels puts dL/dy = 2 (y - t) / N at 2^8 .. 2^9 times (y - t), inside
+// FP16's normal range for |y - t| between about 2^-22 and 2^7; the weight and
+// bias gradients are divided by S (exactly) when their partial sums are added.
 //
 // Kernels (one thread per pixel unless stated):
 //   layer1_kernel      x -> a1 (VALU, 288 FMA per pixel)
-//   mid_kernel         a -> relu(conv(a)) for the 32 -> 32 layers on the matrix
+//   mid_kernel<false>  a -> relu(conv(a)) for the 32 -> 32 layers on the matrix
 //                      cores: per wave, 16 pixels x 32 output channels, K = 9 taps
 //                      x 32 input channels as nine v_mfma_f32_16x16x32_f16 per
 //                      16-channel half; lane (i, g) loads 8 channels (16 bytes)
 //                      of its pixel's neighbour and gets 4 output channels.
+//   mid_kernel<true>   g_l from g_(l+1) through a 32 -> 32 layer: the same
+//                      implicit GEMM with the layer's weights transposed (input
+//                      and output channels swapped) and the taps mirrored, and
+//                      the ReLU mask of a_l in place of bias and ReLU
 //   layer4_kernel      a3 -> y, and either the output pixel or the loss terms and
-//                      dL/dy (training)
-//   bwd4_kernel        dL/da3 through layer 4 and the ReLU of a3
-//   bwd_mid_kernel     dL/da through a 32 -> 32 layer and the ReLU of its input
-//   wgrad_kernel       weight and bias gradients of a layer, first stage: each
-//                      workgroup sums its pixels' products into a partial row
-//   reduce_kernel      second stage: adds the partial rows (no atomics)
+//                      S dL/dy (training)
+//   bwd4_kernel        g3 from dL/dy through layer 4 and the ReLU of a3 (VALU)
+//   wgrad_mid_kernel   weight and bias gradients of a 32 -> 32 layer as a GEMM
+//                      over pixels, K = 32 pixels of one image row per
+//                      instruction: three waves per workgroup, one per tap row
+//   wgrad_edge_kernel  the same for layer 1 (x against g1) and layer 4 (a3
+//                      against dL/dy), with the nine taps as the GEMM's columns
+//   reduce_kernel      second stage of the weight gradients: adds the partial
+//                      rows of all workgroups in a fixed order and scales them
+//   loss_reduce_kernel the training loss from per-workgroup partial sums, in a
+//                      fixed order
 //   adam_kernel        Adam with bias correction
 //   init_kernel        the initial parameters from a seed (Philox4x32-10)
 #pragma once
@@ -146,18 +163,26 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const floa
   }
 }
 
-// aout = relu(conv(ain; W, b)) for a 32 -> 32 layer on the matrix cores.
+// aout = relu(conv(ain; W, b)) for a 32 -> 32 layer on the matrix cores
+// (kBwd = false), or the backward signal of its input (kBwd = true):
+//   aout[q][ci] = (mask[q][ci] > 0) sum_t sum_co W[co][ci][t] ain[q - offset(t)][co],
+// which is the same convolution with input and output channels swapped and the
+// taps mirrored (offset(8 - t) = -offset(t)), applied to the scaled FP16 signal
+// `ain` of the layer above; `mask` is the layer's input activation.
 // Operands of v_mfma_f32_16x16x32_f16 for tap t and output half m (lane i, g):
-//   A[i][8g+e] = W[16m + i][8g + e][t], B[8g+e][i] = ain[neighbour t of pixel i][8g + e],
-//   D[4g+r][i] = output channel 16m + 4g + r of pixel i.
+//   A[i][8g+e] = W'[16m + i][8g + e][t], B[8g+e][i] = ain[neighbour t of pixel i][8g + e],
+//   D[4g+r][i] = output channel 16m + 4g + r of pixel i,
+// with W' = W forward and W'[o][c][t] = W[c][o][8 - t] backward.
 // A wave computes kRows vertically adjacent tiles of 16 pixels (rows r0 .. r0 +
 // kRows - 1, columns c0 .. c0 + 15 of one image): each of the kRows + 2 input rows
 // x 3 column offsets is loaded once and feeds every output row whose 3x3 window
 // covers it, so a tile needs (kRows + 2) * 3 / kRows loads instead of 9.  The
 // image, row and column of a tile are the same for the whole wave.
+template <bool kBwd>
 __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float16 *__restrict__ ain,
                                                        const _Float16 *__restrict__ wh_layer,
                                                        const float *__restrict__ bias,
+                                                       const _Float16 *__restrict__ mask,
                                                        _Float16 *__restrict__ aout, int64_t npix, int64_t ntiles) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
@@ -167,12 +192,14 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) wa[t][m][e] = wh_layer[((16 * m + i) * kC + 8 * g + e) * 9 + t];
+      for (int e = 0; e < 8; ++e)
+        wa[t][m][e] = kBwd ? wh_layer[((8 * g + e) * kC + 16 * m + i) * 9 + (8 - t)]
+                           : wh_layer[((16 * m + i) * kC + 8 * g + e) * 9 + t];
   float bv[2][4];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bv[m][r] = bias[16 * m + 4 * g + r];
+    for (int r = 0; r < 4; ++r) bv[m][r] = kBwd ? 0.0f : bias[16 * m + 4 * g + r];
   const uint32_t col_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
   const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
   const uint32_t step = gridDim.x * (kThreads / 64);
@@ -224,9 +251,19 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
           uint32_t hb[4];
+          if constexpr (kBwd) {
+            const uint2 mw = *reinterpret_cast<const uint2 *>(mask + p * kC + 16 * m + 4 * g);
+            const uint32_t mv[4] = {mw.x & 0xffffu, mw.x >> 16, mw.y & 0xffffu, mw.y >> 16};
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            hb[q] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][q] + bv[m][q], 0.0f)));
+            for (int q = 0; q < 4; ++q) {
+              const float a = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(mv[q])));
+              hb[q] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(a > 0.0f ? acc[j][m][q] : 0.0f));
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              hb[q] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][q] + bv[m][q], 0.0f)));
+          }
           *reinterpret_cast<uint2 *>(aout + p * kC + 16 * m + 4 * g) =
               make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
         }
@@ -236,16 +273,17 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
 }
 
 // y = x + conv(a3; W4, b4).  kTrain = false: writes the output pixel to `out`
-// (clamp(floor(255 y + 1/2))).  kTrain = true: y to y_out (if not null),
-// dL/dy = grad_scale (y - t) to g4, and the sum of (y - t)^2 to *sq (one atomic
-// per wave).  A thread computes kRows vertically adjacent pixels of one column:
-// each of the kRows + 2 neighbour rows x 3 columns is loaded and converted once.
+// (clamp(floor(255 y + 1/2))).  kTrain = true: y to y_out (if not null), the
+// scaled signal S dL/dy = fp16(fp32(grad_scale (y - t)) S) to g4, and the
+// workgroup's sum of (y - t)^2 to sq[blockIdx.x] (summed in a fixed order).  A
+// thread computes kRows vertically adjacent pixels of one column: each of the
+// kRows + 2 neighbour rows x 3 columns is loaded and converted once.
 template <bool kTrain>
 __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Float16 *__restrict__ a3,
                                                           const float *__restrict__ wq, int64_t ngroups,
                                                           uint8_t *__restrict__ out, int out_stride,
-                                                          float *__restrict__ y_out, float *__restrict__ g4,
-                                                          double *__restrict__ sq, float grad_scale) {
+                                                          float *__restrict__ y_out, _Float16 *__restrict__ g4,
+                                                          double *__restrict__ sq, float grad_scale, float S) {
   double local = 0.0;
   const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
   for (int64_t gidx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; gidx < ngroups;
@@ -297,7 +335,8 @@ __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Flo
       } else {
         const float e = y - plane_px(s, s.orig, b, r, c) * kInv255;
         if (y_out) y_out[p] = y;
-        g4[p] = grad_scale * e;
+        const float gv = grad_scale * e;
+        g4[p] = static_cast<_Float16>(gv * S);
         local += static_cast<double>(e) * e;
       }
     }
@@ -305,14 +344,23 @@ __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Flo
   if constexpr (kTrain) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, 64);
-    if ((threadIdx.x & 63) == 0 && local != 0.0) atomicAdd(sq, local);
+    __shared__ double wsum[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
+      sq[blockIdx.x] = t;
+    }
   }
 }
 
-// g3 = (a3 > 0) * dL/da3, dL/da3[q][ci] = sum_t W4[ci][t] g4[q - offset(t)]
-__global__ __launch_bounds__(kThreads) void bwd4_kernel(ImageSet s, const float *__restrict__ g4,
+// S g3 = (a3 > 0) S dL/da3 with S dL/da3[q][ci] = sum_t W4[ci][t] (S g4)[q - offset(t)]
+// (FP32 sums of the FP16 signal), stored as FP16
+__global__ __launch_bounds__(kThreads) void bwd4_kernel(ImageSet s, const _Float16 *__restrict__ g4,
                                                         const _Float16 *__restrict__ a3,
-                                                        const float *__restrict__ wq, float *__restrict__ g3,
+                                                        const float *__restrict__ wq, _Float16 *__restrict__ g3,
                                                         int64_t npix) {
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; p < npix;
        p += static_cast<int64_t>(gridDim.x) * kThreads) {
@@ -321,132 +369,217 @@ __global__ __launch_bounds__(kThreads) void bwd4_kernel(ImageSet s, const float 
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int64_t nb = nb_id(s, q, 1 - t / 3, 1 - t % 3);
-      gv[t] = nb >= 0 ? g4[nb] : 0.0f;
+      gv[t] = nb >= 0 ? static_cast<float>(g4[nb]) : 0.0f;
     }
-    const _Float16 *ap = a3 + p * kC;
-    float4 *dst = reinterpret_cast<float4 *>(g3 + p * kC);
+    const uint4 *ap = reinterpret_cast<const uint4 *>(a3 + p * kC);
+    uint4 *dst = reinterpret_cast<uint4 *>(g3 + p * kC);
 #pragma unroll
-    for (int k = 0; k < kC / 4; ++k) {
-      float o[4];
+    for (int k = 0; k < kC / 8; ++k) {
+      const h8 av = __builtin_bit_cast(h8, ap[k]);
+      h8 o;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int ci = 4 * k + j;
+      for (int j = 0; j < 8; ++j) {
+        const int ci = 8 * k + j;
         float acc = 0.0f;
 #pragma unroll
         for (int t = 0; t < 9; ++t) acc += wq[kW4 + ci * 9 + t] * gv[t];
-        o[j] = static_cast<float>(ap[ci]) > 0.0f ? acc : 0.0f;
+        o[j] = static_cast<_Float16>(static_cast<float>(av[j]) > 0.0f ? acc : 0.0f);
       }
-      dst[k] = make_float4(o[0], o[1], o[2], o[3]);
+      dst[k] = __builtin_bit_cast(uint4, o);
     }
   }
 }
 
-// gin = (ain > 0) * dL/dain through a 32 -> 32 layer:
-//   dL/dain[q][ci] = sum_t sum_co W[co][ci][t] gout[q - offset(t)][co]
-__global__ __launch_bounds__(kThreads) void bwd_mid_kernel(ImageSet s, const float *__restrict__ gout,
-                                                           const _Float16 *__restrict__ ain,
-                                                           const float *__restrict__ wq_layer,
-                                                           float *__restrict__ gin, int64_t npix) {
-  __shared__ float wl[kC * kC * 9];  // [t][co][ci]
-  for (int k = threadIdx.x; k < kC * kC * 9; k += kThreads) {
-    const int t = k / (kC * kC), co = (k / kC) % kC, ci = k % kC;
-    wl[k] = wq_layer[(co * kC + ci) * 9 + t];
-  }
-  __syncthreads();
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; p < npix;
-       p += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const Pix q = pix_of(s, p);
-    float acc[kC];
+// Weight and bias gradients as GEMMs over pixels on the matrix cores, first
+// stage.  The contraction runs over "chunks": 32 consecutive pixels of one image
+// row (columns c0 .. c0 + 31, c0 a multiple of 32; columns past the image width
+// contribute zeros).  Lane (j, g) of a wave (j = lane % 16, g = lane / 16)
+// supplies pixels c0 + 8g .. c0 + 8g + 7 of the chunk to both operands of
+// v_mfma_f32_16x16x32_f16, whose D[4g + r][j] it then holds.  Workgroup w takes
+// chunks w cpw .. w cpw + cpw - 1 and writes one partial row of FP32 sums (of the
+// scaled signals) to part[w]; reduce_kernel adds the rows.
+inline constexpr int kNWMid = kC * kC * 9 + kC;  // partial row of a 32 -> 32 layer
+inline constexpr int kNWEdge = kC * 9 + kC;      // partial row of layer 1 (layer 4 uses 9 kC + 1)
+
+struct Chunk {
+  int b, r, c;  // image, row, first column of this lane's eight pixels
+};
+
+__device__ __forceinline__ Chunk chunk_of(const ImageSet &s, uint32_t chunk, int g) {
+  const uint32_t segs = (static_cast<uint32_t>(s.w) + 31u) / 32u;
+  const uint32_t row = chunk / segs;
+  Chunk k;
+  k.b = static_cast<int>(row / static_cast<uint32_t>(s.h));
+  k.r = static_cast<int>(row - static_cast<uint32_t>(k.b) * static_cast<uint32_t>(s.h));
+  k.c = static_cast<int>((chunk - row * segs) * 32u) + 8 * g;
+  return k;
+}
+
+// 32 -> 32 layer: dW[co][ci][t] = sum_p g[p][co] a[p + offset(t)][ci], db[co] = sum_p g[p][co]
+// (g the scaled FP16 signal of the layer's pre-activation, a its FP16 input).
+// A[j][8g+e] = g[pixel e][16m + j], B[8g+e][j] = a[pixel e + offset(t)][16n + j].
+// Three waves per workgroup; wave dy computes the taps (dy, 0..2) for all four
+// 16 x 16 (co, ci) tiles: the ten input pixels c - 1 .. c + 8 of its tap row give
+// the three column offsets' operands.  Wave 0 also sums the bias gradients.
+__global__ __launch_bounds__(192) void wgrad_mid_kernel(ImageSet s, const _Float16 *__restrict__ g,
+                                                         const _Float16 *__restrict__ a, float *__restrict__ part,
+                                                         uint32_t nchunks, uint32_t cpw) {
+  const int dy = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int l = threadIdx.x & 63, j = l & 15, gq = l >> 4;
+  f4 acc[3][2][2];
 #pragma unroll
-    for (int ci = 0; ci < kC; ++ci) acc[ci] = 0.0f;
-    for (int t = 0; t < 9; ++t) {
-      const int64_t nb = nb_id(s, q, 1 - t / 3, 1 - t % 3);
-      if (nb < 0) continue;
-      const float4 *gp = reinterpret_cast<const float4 *>(gout + nb * kC);
-      for (int c4 = 0; c4 < kC / 4; ++c4) {
-        const float4 gg = gp[c4];
-        const float gvals[4] = {gg.x, gg.y, gg.z, gg.w};
+  for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float *wrow = wl + (t * kC + 4 * c4 + j) * kC;
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int ci = 0; ci < kC; ++ci) acc[ci] += wrow[ci] * gvals[j];
-        }
+      for (int n = 0; n < 2; ++n) acc[dx][m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum[2] = {0.0f, 0.0f};
+  const uint32_t first = blockIdx.x * cpw, last = min(first + cpw, nchunks);
+  const _Float16 zero = static_cast<_Float16>(0.0f);
+  for (uint32_t chunk = first; chunk < last; ++chunk) {
+    const Chunk k = chunk_of(s, chunk, gq);
+    const int64_t row = static_cast<int64_t>(k.b) * s.h + k.r;
+    h8 A[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        A[m][e] = k.c + e < s.w ? g[(row * s.w + k.c + e) * kC + 16 * m + j] : zero;
+    if (dy == 0) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum[m] += static_cast<float>(A[m][e]);
+    }
+    const int rr = k.r + dy - 1;
+    const bool row_ok = rr >= 0 && rr < s.h;
+    const int64_t nrow = static_cast<int64_t>(k.b) * s.h + rr;
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      _Float16 v[10];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) {
+        const int cc = k.c - 1 + e;
+        v[e] = row_ok && cc >= 0 && cc < s.w ? a[(nrow * s.w + cc) * kC + 16 * n + j] : zero;
+      }
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        h8 B;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) B[e] = v[dx + e];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+          acc[dx][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[m], B, acc[dx][m][n], 0, 0, 0);
       }
     }
-    const _Float16 *ap = ain + p * kC;
-    float4 *dst = reinterpret_cast<float4 *>(gin + p * kC);
+  }
+  float *dst = part + static_cast<size_t>(blockIdx.x) * kNWMid;
 #pragma unroll
-    for (int k = 0; k < kC / 4; ++k) {
-      float o[4];
+  for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) o[j] = static_cast<float>(ap[4 * k + j]) > 0.0f ? acc[4 * k + j] : 0.0f;
-      dst[k] = make_float4(o[0], o[1], o[2], o[3]);
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dst[((16 * m + 4 * gq + r) * kC + 16 * n + j) * 9 + dy * 3 + dx] = acc[dx][m][n][r];
+  if (dy == 0) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float t = bsum[m];
+      t += __shfl_xor(t, 16, 64);
+      t += __shfl_xor(t, 32, 64);
+      if (gq == 0) dst[kC * kC * 9 + 16 * m + j] = t;
     }
   }
 }
 
-// Weight and bias gradients of one layer, first stage:
-//   dW[co][ci][t] = sum_p gout[p][co] in[p + offset(t)][ci],  db[co] = sum_p gout[p][co],
-// with `in` the FP16 activations (CI = 32) or the decoded plane / 255 (CI = 1).
-// Workgroup w sums `per_wg` consecutive pixels and writes its partial sums to
-// part[w][0 .. CO CI 9 + CO) (weights, then biases); reduce_kernel adds the
-// partials of all workgroups.  Thread k owns co = k / GROUPS and CPT = CI / GROUPS
-// input channels.
-template <int CI, int CO>
-__global__ __launch_bounds__(kThreads) void wgrad_kernel(ImageSet s, const float *__restrict__ gout,
-                                                         const _Float16 *__restrict__ ain, float *__restrict__ part,
-                                                         int64_t npix, int per_wg) {
-  constexpr int GROUPS = CI >= 4 ? (kThreads / CO < CI / 4 ? kThreads / CO : CI / 4) : 1;
-  constexpr int CPT = CI / GROUPS;
-  constexpr int NW = CO * CI * 9 + CO;
-  static_assert(CO * GROUPS <= kThreads, "one thread per (co, group)");
-  const int k = threadIdx.x;
-  const bool active = k < CO * GROUPS;
-  const int co = active ? k / GROUPS : 0, grp = active ? k % GROUPS : 0;
-  float acc[CPT][9];
-  float accb = 0.0f;
+// Layers 1 and 4, with the nine taps as the GEMM's columns (j < 9; columns 9 .. 15
+// are zero):
+//   kFirst: dW1[co][t] = sum_p g1[p][co] P[p + offset(t)], db1[co] = sum_p g1[p][co],
+//           A[j][8g+e] = g1[pixel e][16m + j], B[8g+e][t] = P[pixel e + offset(t)],
+//           with P the decoded pixel values 0..255 (exact in FP16; reduce_kernel
+//           applies the 1/255 of x = P / 255);
+//   else:   dW4[ci][t] = sum_q a3[q][ci] g4[q - offset(t)], db4 = sum_q g4[q],
+//           A[j][8g+e] = a3[pixel e][16m + j], B[8g+e][t] = g4[pixel e - offset(t)].
+// One wave per workgroup.
+template <bool kFirst>
+__global__ __launch_bounds__(64) void wgrad_edge_kernel(ImageSet s, const _Float16 *__restrict__ act,
+                                                         const _Float16 *__restrict__ g4, float *__restrict__ part,
+                                                         uint32_t nchunks, uint32_t cpw) {
+  constexpr int NW = kFirst ? kNWEdge : kC * 9 + 1;
+  const int l = threadIdx.x & 63, j = l & 15, gq = l >> 4;
+  const int tdy = j / 3 - 1, tdx = j % 3 - 1;  // this lane's tap offset (j < 9)
+  f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+  float bsum[2] = {0.0f, 0.0f};
+  const uint32_t first = blockIdx.x * cpw, last = min(first + cpw, nchunks);
+  const _Float16 zero = static_cast<_Float16>(0.0f);
+  for (uint32_t chunk = first; chunk < last; ++chunk) {
+    const Chunk k = chunk_of(s, chunk, gq);
+    const int64_t row = static_cast<int64_t>(k.b) * s.h + k.r;
+    h8 A[2], B;
 #pragma unroll
-  for (int j = 0; j < CPT; ++j)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc[j][t] = 0.0f;
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * per_wg;
-  const int64_t p1 = p0 + per_wg < npix ? p0 + per_wg : npix;
-  if (active) {
-    for (int64_t p = p0; p < p1; ++p) {
-      const float gv = gout[p * CO + co];
-      accb += gv;
-      const Pix q = pix_of(s, p);
+      for (int e = 0; e < 8; ++e)
+        A[m][e] = k.c + e < s.w ? act[(row * s.w + k.c + e) * kC + 16 * m + j] : zero;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        if constexpr (CI == 1) {
-          acc[0][t] += gv * plane_px(s, s.plane, q.b, q.r + t / 3 - 1, q.c + t % 3 - 1) * kInv255;
-        } else {
-          const int64_t nb = nb_id(s, q, t / 3 - 1, t % 3 - 1);
-          if (nb >= 0) {
-            const _Float16 *ap = ain + nb * CI + grp * CPT;
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) acc[j][t] += gv * static_cast<float>(ap[j]);
-          }
-        }
+    for (int e = 0; e < 8; ++e) {
+      if constexpr (kFirst) {
+        // plane_px is 0 outside the image and the plane; pixels past the row's
+        // end meet A = 0
+        B[e] = j < 9 ? static_cast<_Float16>(plane_px(s, s.plane, k.b, k.r + tdy, k.c + e + tdx)) : zero;
+      } else {
+        const int rr = k.r - tdy, cc = k.c + e - tdx;
+        B[e] = j < 9 && k.c + e < s.w && rr >= 0 && rr < s.h && cc >= 0 && cc < s.w
+                   ? g4[(static_cast<int64_t>(k.b) * s.h + rr) * s.w + cc]
+                   : zero;
       }
     }
-    float *dst = part + static_cast<size_t>(blockIdx.x) * NW;
+    if constexpr (kFirst) {
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int t = 0; t < 9; ++t) dst[(co * CI + grp * CPT + j) * 9 + t] = acc[j][t];
-    if (grp == 0) dst[CO * CI * 9 + co] = accb;
+        for (int e = 0; e < 8; ++e) bsum[m] += static_cast<float>(A[m][e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bsum[0] += j == 4 ? static_cast<float>(B[e]) : 0.0f;  // centre tap: g4[q]
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[m], B, acc[m], 0, 0, 0);
+  }
+  float *dst = part + static_cast<size_t>(blockIdx.x) * NW;
+  if (j < 9) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[(16 * m + 4 * gq + r) * 9 + j] = acc[m][r];
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    float t = bsum[m];
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    bsum[m] = t;
+  }
+  if constexpr (kFirst) {
+    if (gq == 0) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) dst[kC * 9 + 16 * m + j] = bsum[m];
+    }
+  } else {
+    if (l == 4) dst[kC * 9] = bsum[0];
   }
 }
 
-// Second stage: dW[k] = sum over workgroups of part[w][k] for the nw weights,
-// db[k] likewise for the nb biases stored after them.  A workgroup reduces 64
-// consecutive entries; its four waves take every fourth partial row each (the
-// loads of a lane are independent, so many are in flight), then add their
-// four sums in LDS.
+// Second stage: dW[k] = wscale * (sum over workgroups of part[w][k]) for the nw
+// weights, db[k] likewise with bscale for the nb biases stored after them.  A
+// workgroup reduces 64 consecutive entries; its four waves take every fourth
+// partial row each (the loads of a lane are independent, so many are in flight),
+// then add their four sums in LDS: a fixed order, so the result is deterministic.
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restrict__ part, int nwg, int nw, int nb,
-                                                          float *__restrict__ dW, float *__restrict__ db) {
+                                                          float *__restrict__ dW, float *__restrict__ db,
+                                                          float wscale, float bscale) {
   constexpr int kWaves = kThreads / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = nw + nb;
@@ -464,9 +597,9 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 #pragma unroll
     for (int j = 0; j < kWaves; ++j) t += sums[j][lane];
     if (k < nw)
-      dW[k] = t;
+      dW[k] = t * wscale;
     else
-      db[k - nw] = t;
+      db[k - nw] = t * bscale;
   }
 }
 
@@ -486,14 +619,19 @@ __global__ __launch_bounds__(kThreads) void adam_kernel(float *__restrict__ p, f
   }
 }
 
-__global__ __launch_bounds__(kThreads) void zero_f32_kernel(float *__restrict__ a, int64_t n) {
-  for (int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; k < n;
-       k += static_cast<int64_t>(gridDim.x) * kThreads)
-    a[k] = 0.0f;
-}
-
-__global__ void mean_kernel(const double *__restrict__ sq, double *__restrict__ loss, double inv_n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *loss = *sq * inv_n;
+// loss = inv_n * (sum of the n per-workgroup partial sums), added in a fixed order
+__global__ __launch_bounds__(kThreads) void loss_reduce_kernel(const double *__restrict__ sq, int n,
+                                                               double *__restrict__ loss, double inv_n) {
+  double t = 0.0;
+  for (int k = threadIdx.x; k < n; k += kThreads) t += sq[k];
+  __shared__ double part[kThreads];
+  part[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = part[0] * inv_n;
 }
 
 // Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and Shaw

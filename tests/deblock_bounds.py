@@ -253,10 +253,17 @@ def gradient_tolerance(E, g16=True, depth=None):
     return np.concatenate(out) + 1e-30
 
 
-def emulate(p, x, t, g16=True, scale=2.0 ** 20):
+def signal_scale(n):
+    """The GPU's scale of the FP16 backward signals for a batch of n pixels:
+    2^(floor(log2 n) + 8)."""
+    return 2.0 ** (int(n).bit_length() - 1 + 8)
+
+
+def emulate(p, x, t, g16=True, scale=None):
     """The network's forward and backward pass in the GPU's arithmetic: FP32
     products and sums (BLAS order), activations stored as FP16, backward signals
-    rounded to FP16 after multiplying by `scale` when g16.  Returns (y, grad)."""
+    rounded to FP16 after multiplying by `scale` (default: the GPU's, from the
+    batch's pixel count) when g16.  Returns (y, grad)."""
     f32, f16 = np.float32, np.float16
     L = [(w.astype(f32), b.astype(f32)) for w, b in layers(p)]
     inv = f32(1.0) / f32(255.0)
@@ -271,6 +278,8 @@ def emulate(p, x, t, g16=True, scale=2.0 ** 20):
             a.append(np.maximum(zz, f32(0)).astype(f16).astype(f32))
     y = (xp + z[3]).astype(f32)
     N = y.size
+    if scale is None:
+        scale = signal_scale(N)
     g = [None] * 4
     g[3] = (f32(2.0 / N) * (y - tt)).astype(f32)
 

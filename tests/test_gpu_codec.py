@@ -272,6 +272,19 @@ def test_accumulate_over_bands(hip, oracle_mod, torch_mod):
         assert np.array_equal(np.concatenate([host(q_top), host(q_bot)]), oq)
 
 
+@pytest.mark.parametrize("W,H,qs", [(512, 512, 4), (1, 1, 4), (13, 5, 2), (1024, 814, 8), (333, 97, 16),
+                                    (2048, 1536, 4)])
+def test_row_mapping_bit_exact(hip, oracle_mod, W, H, qs):
+    # the lane-per-row codec (LDS transposes) against the oracle, with padded strides
+    img = synth(W, H, 40 + W % 7)
+    src = to_dev(img, stride=((W + 7) // 8) * 8 + 16)
+    dst, sse, q = hip.dct_codec_rows(src, qs, want_qcoef=True)
+    rec, osse, oq = oracle_mod.cordic_codec(img, qs, want_q=True)
+    assert int(host(sse)[0]) == osse
+    assert np.array_equal(host(q), oq)
+    assert np.array_equal(host(dst), rec)
+
+
 def test_invalid_arguments_raise(hip, torch_mod):
     src = to_dev(synth(16, 16, 1))
     with pytest.raises(hip.DctError) as e:
@@ -300,6 +313,11 @@ def test_full_size_8192(hip, oracle_mod):
     assert sse_h == osse
     assert np.array_equal(q_h, oq)
     assert np.array_equal(rec_h, orec)
+    say("[gpu] 8192x8192 fused codec, lane-per-row mapping")
+    d_rows, s_rows = hip.dct_codec_rows(src, 4)
+    assert int(host(s_rows)[0]) == osse
+    assert np.array_equal(host(d_rows), orec)
+    del d_rows
     say("[gpu] 8192x8192 fused codec, accumulating entry point (the benchmark's)")
     import torch
     acc = torch.zeros(1, dtype=torch.int64, device="cuda")
