@@ -179,11 +179,12 @@ DeblockLayout deblock_layout(int64_t npix, bool training) {
   L.sq = o;
   o += align256(sizeof(double) * kLossGroups);
   const size_t act = align256(sizeof(_Float16) * dct::db::kC * static_cast<size_t>(npix));
+  // inference runs in one launch with its activations in LDS: only the weights
   L.a1 = o;
-  o += act;
+  if (training) o += act;
   L.a2 = o;
-  o += act;
-  L.a3 = training ? o : L.a1;  // inference writes the third activation over the first
+  if (training) o += act;
+  L.a3 = o;
   if (training) o += act;
   L.g4 = o;
   if (training) o += align256(sizeof(_Float16) * static_cast<size_t>(npix));
@@ -224,6 +225,17 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
   auto *g4 = reinterpret_cast<_Float16 *>(ws + L.g4);
   prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
+  if (out != nullptr) {
+    // inference: one workgroup per 28 x 26 output tile, everything in LDS
+    constexpr int lds = kLdsA1 + kLdsA2 + kLdsX;
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_apply_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (attr != hipSuccess) return DCT_ERR_DEVICE;
+    const unsigned tiles = static_cast<unsigned>(((set.w + kTW - 1) / kTW) * ((set.h + kTH - 1) / kTH));
+    fused_apply_kernel<<<tiles, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, wq, wh, out, out_stride);
+    return launched();
+  }
   // layer 1 and layer 4: one thread per kRows vertically adjacent pixels of a column
   const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
   layer1_kernel<<<px_grid(ngroups), kThreads, 0, s>>>(set, wq, a1, ngroups);
@@ -232,11 +244,6 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, nullptr, a2, npix, ntiles);
   mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, nullptr, a3, npix, ntiles);
-  if (out != nullptr) {
-    layer4_kernel<false><<<px_grid(ngroups), kThreads, 0, s>>>(set, a3, wq, ngroups, out, out_stride, nullptr,
-                                                               nullptr, nullptr, 0.0f, 0.0f);
-    return launched();
-  }
   const unsigned lgrid = static_cast<unsigned>(std::min<int64_t>((ngroups + kThreads - 1) / kThreads, kLossGroups));
   layer4_kernel<true><<<lgrid, kThreads, 0, s>>>(set, a3, wq, ngroups, nullptr, 0, y, g4, sq,
                                                  2.0f / static_cast<float>(npix), signal_scale(npix));

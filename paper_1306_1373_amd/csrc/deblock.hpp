@@ -37,6 +37,8 @@
 //                      the ReLU mask of a_l in place of bias and ReLU
 //   layer4_kernel      a3 -> y, and either the output pixel or the loss terms and
 //                      S dL/dy (training)
+//   fused_apply_kernel inference in one launch: all four layers of a 28 x 26
+//                      output tile with x, a1, a2 and a3 held in LDS
 //   bwd4_kernel        g3 from dL/dy through layer 4 and the ReLU of a3 (VALU)
 //   wgrad_mid_kernel   weight and bias gradients of a 32 -> 32 layer as a GEMM
 //                      over pixels, K = 32 pixels of one image row per
@@ -272,6 +274,13 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
   }
 }
 
+// y = p / 255 + net for a decoded pixel p: the quotient rounded on its own, then
+// the sum (no fused multiply-add), identically in every kernel that forms y
+__device__ __forceinline__ float residual(float p, float net) {
+#pragma clang fp contract(off)
+  return p * kInv255 + net;
+}
+
 // y = x + conv(a3; W4, b4).  kTrain = false: writes the output pixel to `out`
 // (clamp(floor(255 y + 1/2))).  kTrain = true: y to y_out (if not null), the
 // scaled signal S dL/dy = fp16(fp32(grad_scale (y - t)) S) to g4, and the
@@ -327,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Flo
     for (int j = 0; j < kRows; ++j) {
       const int r = r0 + j;
       if (r >= s.h) break;
-      const float y = plane_px(s, s.plane, b, r, c) * kInv255 + acc[j];
+      const float y = residual(plane_px(s, s.plane, b, r, c), acc[j]);
       const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
       if constexpr (!kTrain) {
         const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
@@ -600,6 +609,226 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
       dW[k] = t * wscale;
     else
       db[k - nw] = t * bscale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference in one launch: the four layers of a tile with every activation in LDS
+// ---------------------------------------------------------------------------
+//
+// A workgroup of kFThreads threads computes an output tile of kTW x kTH pixels
+// of one image.  Each layer is computed on the region the next one reads (one
+// pixel more on every side), so the tile's x, a1, a2 and a3 never leave LDS and
+// only the decoded and the output pixels touch HBM.  Positions outside the image
+// hold zeros at every layer (the network's zero padding).  Every float is
+// computed as in layer1_kernel, mid_kernel<false> and layer4_kernel (same
+// operands, same order of the sums, the same roundings of x = p / 255 and of
+// y), so the output is the rounding of the y those kernels form.
+//
+// Regions, in rows and columns relative to the tile's top-left output pixel:
+//   a3  rows -1 .. 3 kG3 - 2, columns -1 .. 30  (kG3 row groups x two 16-column halves)
+//   a2  rows -2 .. 3 kG2 - 3, columns -2 .. 31  (kG2 groups x two halves; columns 30, 31
+//       are read only by a3 columns past the tile and are never written)
+//   a1  rows -3 .. 3 kG2 - 2, columns -3 .. 30  (one thread per column and three rows)
+//   x   rows -4 .. 3 kG2 - 1, columns -4 .. 31
+inline constexpr int kTW = 28;                          // output columns of a tile
+inline constexpr int kTH = 26;                          // output rows of a tile
+inline constexpr int kFThreads = 512;                   // eight waves
+inline constexpr int kG3 = (kTH + 2 + kRows - 1) / kRows;      // a3 row groups
+inline constexpr int kG2 = (3 * kG3 + 2 + kRows - 1) / kRows;  // a2 row groups (cover a3's rows +- 1)
+inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = kR2 + 2, kRX = kR1 + 2;  // rows held
+inline constexpr int kC3 = 32, kC2 = 34, kC1 = 34, kCX = 36;                      // columns held
+inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; a3 later reuses this space
+inline constexpr int kLdsA2 = kR2 * kC2 * kC * 2;
+inline constexpr int kLdsX = kRX * kCX * 4;
+static_assert(kR3 * kC3 * kC * 2 <= kLdsA1, "a3 fits in a1's space");
+static_assert(kLdsA1 + kLdsA2 + kLdsX <= 160 * 1024, "the tile fits in one CU's LDS");
+
+// relu(conv(ain; W, b)) on a 16-pixel x kRows tile of a 32 -> 32 layer, operands
+// from LDS.  `ain` holds a region of cin columns whose column 0 is one to the
+// left of this tile's column 0 and whose row 0 is one above its row 0; the tile
+// writes rows 0 .. kRows - 1 and columns i of `aout` (cout columns per row),
+// zero where the image position (img_r0 + j, img_c0 + i) lies outside the image.
+__device__ __forceinline__ void fused_mid_tile(const _Float16 *ain, int cin, int rin0, int cin0,
+                                               const h8 (&wa)[9][2], const float (&bv)[2][4], _Float16 *aout,
+                                               int cout, int rout0, int cout0, int img_r0, int img_c0, int H,
+                                               int W) {
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  f4 acc[kRows][2];
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) acc[j][0] = acc[j][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < kRows + 2; ++k) {  // input row (rin0 + k), image row img_r0 - 1 + k
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const h8 bx = *reinterpret_cast<const h8 *>(ain + ((rin0 + k) * cin + cin0 + i + dx) * kC + 8 * g);
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const int dy = k - j;
+        if (dy >= 0 && dy <= 2) {
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+            acc[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[dy * 3 + dx][m], bx, acc[j][m], 0, 0, 0);
+        }
+      }
+    }
+  }
+  const int c = img_c0 + i;
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int r = img_r0 + j;
+    const bool in = r >= 0 && r < H && c >= 0 && c < W;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      uint32_t hb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        hb[q] = in ? __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][q] + bv[m][q], 0.0f))) : 0u;
+      *reinterpret_cast<uint2 *>(aout + ((rout0 + j) * cout + cout0 + i) * kC + 16 * m + 4 * g) =
+          make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+    }
+  }
+}
+
+__device__ __forceinline__ void load_mid_weights(const _Float16 *__restrict__ wh_layer, const float *__restrict__ bias,
+                                                 h8 (&wa)[9][2], float (&bv)[2][4]) {
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) wa[t][m][e] = wh_layer[((16 * m + i) * kC + 8 * g + e) * 9 + t];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[m][r] = bias[16 * m + 4 * g + r];
+}
+
+// The deblocked output plane of one decoded plane (W x H, pitch stride), tile by tile.
+__global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *__restrict__ plane, int W, int H,
+                                                                int stride, const float *__restrict__ wq,
+                                                                const _Float16 *__restrict__ wh,
+                                                                uint8_t *__restrict__ out, int out_stride) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  _Float16 *a1 = reinterpret_cast<_Float16 *>(lds);
+  _Float16 *a3 = a1;  // a1 is dead once a2 is formed
+  _Float16 *a2 = reinterpret_cast<_Float16 *>(lds + kLdsA1);
+  float *xs = reinterpret_cast<float *>(lds + kLdsA1 + kLdsA2);
+  const int tiles_x = (W + kTW - 1) / kTW;
+  const int R0 = static_cast<int>(blockIdx.x) / tiles_x * kTH, C0 = static_cast<int>(blockIdx.x) % tiles_x * kTW;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // the decoded pixels p (as floats) on rows R0 - 4 .., columns C0 - 4 .., zero
+  // outside the image; x = p / 255 is formed where it is used, as in the
+  // one-layer kernels
+  for (int k = tid; k < kRX * kCX; k += kFThreads) {
+    const int rr = R0 - 4 + k / kCX, cc = C0 - 4 + k % kCX;
+    xs[k] = rr >= 0 && rr < H && cc >= 0 && cc < W ? static_cast<float>(plane[static_cast<size_t>(rr) * stride + cc])
+                                                   : 0.0f;
+  }
+  __syncthreads();
+  // layer 1 on rows -3 .. kR1 - 4, columns -3 .. 30: one thread per column and kRows rows
+  constexpr int kG1 = (kR1 + kRows - 1) / kRows;
+  for (int k = tid; k < kG1 * kC1; k += kFThreads) {
+    const int col = k % kC1, r0 = k / kC1 * kRows;  // region coordinates (row 0 = image row R0 - 3)
+    float x[kRows + 2][3];
+#pragma unroll
+    for (int q = 0; q < kRows + 2; ++q)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int xr = r0 + q, xc = col + dx;  // x region: row 0 = image row R0 - 4
+        x[q][dx] = (xr < kRX ? xs[xr * kCX + xc] : 0.0f) * kInv255;
+      }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const int rr = r0 + j;
+      if (rr >= kR1) break;
+      const int ir = R0 - 3 + rr, ic = C0 - 3 + col;
+      const bool in = ir >= 0 && ir < H && ic >= 0 && ic < W;
+      uint32_t words[kC / 2];
+#pragma unroll
+      for (int co = 0; co < kC; ++co) {
+        float acc = wq[kB1 + co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += wq[kW1 + co * 9 + t] * x[j + t / 3][t % 3];
+        const uint32_t hbits = in ? __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc, 0.0f))) : 0u;
+        words[co >> 1] = (co & 1) ? (words[co >> 1] | (hbits << 16)) : hbits;
+      }
+      uint4 *dst = reinterpret_cast<uint4 *>(a1 + (rr * kC1 + col) * kC);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        dst[q] = make_uint4(words[4 * q], words[4 * q + 1], words[4 * q + 2], words[4 * q + 3]);
+    }
+  }
+  __syncthreads();
+  {
+    // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (region row 0 = image row R0 - 3, column 0 = C0 - 3)
+    h8 wa[9][2];
+    float bv[2][4];
+    load_mid_weights(wh + kW2, wq + kB2, wa, bv);
+    for (int task = wave; task < kG2 * 2; task += kFThreads / 64) {
+      const int grp = task >> 1, half = task & 1;
+      const int ro = grp * kRows;  // a2 region row (row 0 = image row R0 - 2)
+      fused_mid_tile(a1, kC1, ro, 16 * half, wa, bv, a2, kC2, ro, 16 * half, R0 - 2 + ro, C0 - 2 + 16 * half, H, W);
+    }
+  }
+  __syncthreads();
+  {
+    // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (region row 0 = image row R0 - 2, column 0 = C0 - 2)
+    h8 wa[9][2];
+    float bv[2][4];
+    load_mid_weights(wh + kW3, wq + kB3, wa, bv);
+    for (int task = wave; task < kG3 * 2; task += kFThreads / 64) {
+      const int grp = task >> 1, half = task & 1;
+      const int ro = grp * kRows;  // a3 region row (row 0 = image row R0 - 1)
+      fused_mid_tile(a2, kC2, ro, 16 * half, wa, bv, a3, kC3, ro, 16 * half, R0 - 1 + ro, C0 - 1 + 16 * half, H, W);
+    }
+  }
+  __syncthreads();
+  // layer 4 on the tile's pixels: one thread per column and kRows rows
+  constexpr int kG4 = (kTH + kRows - 1) / kRows;
+  for (int k = tid; k < kG4 * kTW; k += kFThreads) {
+    const int col = k % kTW, r0 = k / kTW * kRows;
+    const int c = C0 + col;
+    if (c >= W || R0 + r0 >= H) continue;
+    float acc[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) acc[j] = wq[kB4];
+#pragma unroll
+    for (int q = 0; q < kRows + 2; ++q) {  // image row R0 + r0 - 1 + q, a3 region row r0 + q
+      const int rr = R0 + r0 - 1 + q;
+      if (rr < 0 || rr >= H) continue;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int cc = c + dx - 1;
+        if (cc < 0 || cc >= W) continue;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a3 + ((r0 + q) * kC3 + col + dx) * kC);
+        float av[kC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const h8 hv = __builtin_bit_cast(h8, src[u]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) av[8 * u + e] = static_cast<float>(hv[e]);
+        }
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+          const int dy = q - j;
+          if (dy >= 0 && dy <= 2) {
+#pragma unroll
+            for (int ci = 0; ci < kC; ++ci) acc[j] += wq[kW4 + ci * 9 + dy * 3 + dx] * av[ci];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const int r = R0 + r0 + j;
+      if (r0 + j >= kTH || r >= H) break;
+      const float y = residual(xs[(r0 + j + 4) * kCX + col + 4], acc[j]);
+      const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
+      out[static_cast<size_t>(r) * out_stride + c] = static_cast<uint8_t>(v);
+    }
   }
 }
 

@@ -189,10 +189,21 @@ def forward_bands(oracle_mod, pq, x, band=64, threads=16):
     return y, tol
 
 
+def padded_plane(hip, a):
+    """A device plane holding a (H, W) uint8 image with its pitch rounded up to a
+    multiple of 8 (the ABI's rule); pad bytes hold 0xA5."""
+    import torch
+    H, W = a.shape
+    pitch = (W + 7) // 8 * 8
+    buf = torch.full((H, pitch), 0xA5, dtype=torch.uint8, device="cuda")
+    buf[:, :W] = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return buf[:, :W]
+
+
 def check_apply(hip, oracle_mod, dec, params, label):
     pq = fp16_round(params)
     db = hip.Deblocker(params)
-    out = db.apply(to_dev(dec)).cpu().numpy().astype(np.int64)
+    out = db.apply(padded_plane(hip, dec)).cpu().numpy().astype(np.int64)
     x = dec.astype(np.float64) / 255.0
     y_ref, tol = forward_bands(oracle_mod, pq, x)
     v = 255.0 * y_ref + 0.5
@@ -207,6 +218,32 @@ def check_apply(hip, oracle_mod, dec, params, label):
 def test_apply_matches_oracle_pixels(hip, oracle_mod):
     orig, dec = coded_pair(72, 40, 6, 16)
     check_apply(hip, oracle_mod, dec, dbb.he_params(10), "72 x 40")
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (29, 27), (57, 53), (200, 13), (28, 26), (85, 79)])
+def test_apply_ragged_tiles(hip, oracle_mod, W, H):
+    # planes that are not whole numbers of the inference kernel's 28 x 26 tiles,
+    # one smaller than a tile, one exactly one tile
+    orig, dec = coded_pair(W, H, 20 + W, 16)
+    check_apply(hip, oracle_mod, dec, dbb.he_params(21), f"{W} x {H}")
+
+
+@pytest.mark.parametrize("W,H", [(1024, 1024), (85, 79)])
+def test_fused_apply_equals_layer_kernels(hip, W, H):
+    # the one-launch inference computes every float as the one-layer kernels of
+    # the training forward pass do: its pixels are the rounding of their y (the
+    # final 255 y + 1/2 taken with one rounding, as a fused multiply-add, or two)
+    orig, dec = coded_pair(W, H, 30 + H, 20)
+    db = hip.Deblocker(dbb.he_params(23))
+    d = padded_plane(hip, dec)
+    out = db.apply(d).cpu().numpy().astype(np.int64)
+    y = db.forward(d, None, H, W).cpu().numpy()[0]
+    one = np.float32(np.float64(y) * 255.0 + 0.5)
+    two = np.float32(np.float32(255.0) * y) + np.float32(0.5)
+    r1, r2 = (np.clip(np.floor(v), 0, 255).astype(np.int64) for v in (one, two))
+    ok = (out == r1) | (out == r2)
+    say(f"[gpu] fused apply {W} x {H}: {int((r1 != r2).sum())} pixels where the two roundings differ")
+    assert np.all(ok), np.argwhere(~ok)[:8]
 
 
 def test_apply_matches_oracle_1024(hip, oracle_mod):
