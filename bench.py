@@ -82,7 +82,7 @@ def parse():
                          "DIR/commands.txt lists the commands) for the kernels of --kernels into the "
                          "markdown file --out")
     ap.add_argument("--kernels", default="",
-                    help="for --summarize-counters: prefix=label pairs, comma-separated")
+                    help="for --summarize-counters: prefix=label pairs, separated by semicolons")
     ap.add_argument("--pixels", type=float, default=0.0,
                     help="for --summarize-counters: pixels each launch codes (per-pixel rows)")
     ap.add_argument("--title", default="", help="for --summarize-counters: the table's heading")
@@ -107,13 +107,21 @@ PROFILE = os.path.join(ROOT, "profiles", "codec_kernel_8192.json")
 COPY_BYTES = 64 << 20
 
 
+def _name_matches(name, pattern):
+    """True when the kernel name starts with the pattern, or (a pattern with "|")
+    contains any of its parts."""
+    if "|" not in pattern:
+        return name.startswith(pattern)
+    return any(p and p in name for p in pattern.split("|"))
+
+
 def _counter_means(d, prefix):
     import csv
     import glob
     f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[0]
     vals = {}
     for r in csv.DictReader(open(f)):
-        if r["Kernel_Name"].startswith(prefix):
+        if _name_matches(r["Kernel_Name"], prefix):
             vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
@@ -145,6 +153,9 @@ def summarize_profile(root, prefix, out):
         "algorithmic_bytes_per_dispatch": BYTES_PER_PIXEL * W * H,
         "sq": _counter_means(os.path.join(root, "sq"), prefix),
     }
+    cmd_file = os.path.join(root, "commands.txt")
+    if os.path.exists(cmd_file):
+        summary["commands"] = [c.rstrip() for c in open(cmd_file) if c.strip()]
     with open(out, "w") as f:
         json.dump(summary, f, indent=1)
     with open(os.path.splitext(out)[0] + ".md", "w") as f:
@@ -165,7 +176,11 @@ def profile_markdown(d, row):
         f"Digest of the codec kernel's sources and flags when profiled: `{d['kernel_sha256']}`; `bench.py` "
         "reports the traffic below only while they still have this digest.", "",
         "## Commands", "",
-        "Run from `/tmp` with `TMPDIR=/tmp`, `R` the repository root:", "", "```",
+        "Run from `/tmp` with `TMPDIR=/tmp`, `R` the repository root:", "", "```"]
+    if d.get("commands"):
+        lines += d["commands"] + [f"python3 $R/bench.py --summarize-profile DIR  (DIR the folder of the passes)", "```", ""]
+    else:
+        lines += [
         "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof/trace -o run --output-format csv -- "
         "python3 $R/bench.py --steps 50 --warmup 10 --no-cpu-baseline --no-check",
         "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/prof/fetch -o run --output-format csv -- "
@@ -179,7 +194,8 @@ def profile_markdown(d, row):
         "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_VALU2 SQ_INSTS_SALU "
         "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_LDS -d $R/gpurun_out/prof/sq -o run --output-format csv -- "
         "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-check",
-        "python3 $R/bench.py --summarize-profile $R/gpurun_out/prof", "```", "",
+        "python3 $R/bench.py --summarize-profile $R/gpurun_out/prof", "```", ""]
+    lines += [
         f"## Kernel trace ({kt['calls']} launches)", "",
         "| | |", "|---|---|",
         f"| average | {kt['avg_ns'] / 1000:.1f} us |",
@@ -224,7 +240,9 @@ def summarize_counters(root, kernels, pixels, title, out):
     (passes copy_fetch / copy_write), and per-pixel figures."""
     import csv
     import glob
-    pairs = [kv.split("=", 1) for kv in kernels.split(",") if kv]
+    # pattern=label: a kernel matches when any of the pattern's "|"-separated parts
+    # occurs in its name (rocprofv3 reports some names mangled, some demangled)
+    pairs = [kv.split("=", 1) for kv in kernels.split(";") if kv]
     passes = sorted(d for d in os.listdir(root) if os.path.isdir(os.path.join(root, d)))
     counters, trace = {}, {}
     for ps in passes:
@@ -233,7 +251,7 @@ def summarize_counters(root, kernels, pixels, title, out):
             stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))[0]
             for r in csv.DictReader(open(stats)):
                 for pre, lab in pairs:
-                    if r["Name"].startswith(pre):
+                    if _name_matches(r["Name"], pre):
                         trace[lab] = (float(r["AverageNs"]), int(r["Calls"]))
             continue
         if ps.startswith("copy_"):
@@ -856,6 +874,27 @@ def bench_sweep(args):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / ((replays - 1) * reps)
         graph_ok = bool((sse[10:10 + reps] == sse[10]).all().item())
+        # the lane-per-row mapping (dct_codec_rows), eager calls from Python and a
+        # captured graph of its two launches per call (fill kernel and codec)
+        sse_r = torch.zeros(reps, dtype=torch.int64, device=dev)
+        dst_r = codec.new_plane(w, h, dev)
+        codec.dct_codec_rows(src, QS, dst=dst_r, sse=sse_r[0:1])
+        torch.cuda.synchronize()
+        graph_r = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gstream):
+            with torch.cuda.graph(graph_r, stream=gstream):
+                for i in range(reps):
+                    codec.dct_codec_rows(src, QS, dst=dst_r, sse=sse_r[i:i + 1])
+        torch.cuda.synchronize()
+        graph_r.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(replays - 1):
+            graph_r.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_rows = e0.elapsed_time(e1) / ((replays - 1) * reps)
+        rows_ok = bool((sse_r == sse_r[0]).all().item() and torch.equal(dst_r, dst))
         # with copies: pinned host buffers, upload + codec + download on one stream
         hsrc = torch.from_numpy(img).pin_memory()
         hdst = torch.empty((h, w), dtype=torch.uint8).pin_memory()
@@ -873,16 +912,19 @@ def bench_sweep(args):
         ms_copies = e0.elapsed_time(e1) / creps
         rec, osse = bands.codec_bands(img, QS, threads=1)
         parity = bool(np.array_equal(dst.cpu().numpy(), rec) and int(sse[10].item()) == replays * osse
-                      and graph_ok and np.array_equal(hdst.numpy(), rec))
+                      and graph_ok and np.array_equal(hdst.numpy(), rec) and rows_ok
+                      and int(sse_r[0].item()) == osse)
         t1 = _median_time(lambda: bands.codec_bands(img, QS, threads=1), 3)
         tn = _median_time(lambda: bands.codec_bands(img, QS, threads=cores), 3)
         px = w * h
         rows.append({"W": w, "H": h, "gpu_ms": round(ms, 5), "gpu_gpx_s": round(px / ms / 1e6, 3),
                      "gpu_ms_eager_call": round(ms_eager, 5), "gpu_ms_with_copies": round(ms_copies, 5),
+                     "gpu_ms_lane_per_row": round(ms_rows, 5),
                      "cpu_oracle_ms_1core": round(1e3 * t1, 3), f"cpu_oracle_ms_{cores}cores": round(1e3 * tn, 3),
                      "psnr_db": round(codec.psnr_from_sse(osse, w, h), 6), "parity": parity,
                      "paper_cpu_ms": cpu_ms, "paper_gpu_ms": gpu_ms})
-        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.2f} us in a graph ({px / ms / 1e6:.1f} Gpx/s), eager call "
+        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.2f} us in a graph ({px / ms / 1e6:.1f} Gpx/s), lane per row "
+              f"{ms_rows * 1e3:.2f} us, eager call "
               f"{ms_eager * 1e3:.1f} us, with copies "
               f"{ms_copies * 1e3:.1f} us, oracle 1 core {t1 * 1e3:.1f} ms", file=sys.stderr, flush=True)
     print(json.dumps({"workload": "sweep over the image sizes of the paper's timing tables "

@@ -134,11 +134,14 @@ __device__ __forceinline__ uint32_t freconstruct(float x) {
   return static_cast<uint32_t>(__builtin_fminf(__builtin_fmaxf(p, 0.0f), 255.0f));
 }
 
-// The same into byte k of acc for the matrix form, given x + 128 + 1/2 (the
-// inverse product starts its accumulation there): the floor is an integer-valued
-// float, which the saturating byte conversion clamps exactly
+// The same into byte k of acc for the matrix form, given x + 128 (the inverse
+// product starts its accumulation there): the byte conversion rounds to the
+// nearest integer, ties to even, and saturates to [0, 255] (checked on the
+// device), so one instruction rounds and clamps; it differs from floor(x + 128 +
+// 1/2) only when the computed x + 128 is an exact tie, within the form's error
+// of the rounding boundary.
 __device__ __forceinline__ uint32_t pack_reconstruct(float x_offset, uint32_t k, uint32_t acc) {
-  return __builtin_amdgcn_cvt_pk_u8_f32(__builtin_floorf(x_offset), k, acc);
+  return __builtin_amdgcn_cvt_pk_u8_f32(x_offset, k, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +488,7 @@ __device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const Inv
       bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], kc.qv[t][r], kc.rq[t][r]));
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 x = T::mma(inv->ia[t][0][lane], bq[0], f32x4{128.5f, 128.5f, 128.5f, 128.5f});
+    f32x4 x = T::mma(inv->ia[t][0][lane], bq[0], f32x4{128.0f, 128.0f, 128.0f, 128.0f});
     x = T::mma(inv->ia[t][1][lane], bq[1], x);
     uint32_t v = 0;
 #pragma unroll

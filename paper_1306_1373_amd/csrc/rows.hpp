@@ -5,8 +5,8 @@
 // A wave codes eight horizontally consecutive blocks; lane (j, r) = (lane % 8,
 // lane / 8) owns row r of block j for the row passes and column r of block j
 // for the column passes, and the two transposes go through a wave-private LDS
-// tile of the eight blocks (64 int32 each, rows padded to nine words so that the
-// eight lanes of one block never meet in a bank).  Lanes with the same r read
+// tile of the eight blocks (64 int32 each, laid out so that neither the stores
+// nor the loads of a transpose meet in a bank).  Lanes with the same r read
 // and write 64 contiguous bytes of the plane.  Every value is the same integer
 // as in the lane-per-block kernel: the 1-D graphs below perform the same
 // operations as forward_pass / inverse_pass on one line.
@@ -93,8 +93,12 @@ __device__ __forceinline__ void inverse_line(int (&z)[8]) {
 
 inline constexpr int kThreads = 256;               // four waves
 inline constexpr int kMaxGroups = 8192;            // workgroups at most (waves loop over further groups)
+// LDS layout of a wave's tile: element (a, b) of block j (a the pass's output
+// index, b the line) at word 72 j + 9 a + b.  A row-pass store (fixed a, lanes
+// (j, b)) hits words 8 j + b + 9 a (mod 64) and a column-pass load (fixed b, lanes
+// (j, a)) hits 8 j + 9 a + b (mod 64): 64 different banks both ways.
 inline constexpr int kPitch = 9;                   // LDS words per line of a block tile
-inline constexpr int kTile = 8 * kPitch + 1;       // words per block (73: blocks start in different banks)
+inline constexpr int kTile = 8 * kPitch;           // words per block
 
 // a1..a9 under recipe RC, one lane per block row; each wave codes groups of
 // eight blocks, group g = blockIdx.x * 4 + wave, g += gridDim.x * 4
@@ -129,9 +133,24 @@ __global__ __launch_bounds__(kThreads) void codec_rows_kernel(const uint8_t *__r
   uint64_t err = 0;
   const int ngroups = (nblocks + 7) / 8;
   for (int grp = blockIdx.x * (kThreads / 64) + wave; grp < ngroups; grp += gridDim.x * (kThreads / 64)) {
-    const int b = grp * 8 + j;
+    // block grp * 8 + j: one scalar division per group (grp is wave-uniform); a
+    // lane wraps at most once into the next block row when a row holds at least
+    // eight blocks, else it divides
+    const int b0 = grp * 8, b = b0 + j;
     const bool live = b < nblocks;
-    const int by = live ? b / bw : 0, bx = live ? b - (b / bw) * bw : 0;
+    int by, bx;
+    if (bw >= 8) {
+      const int by0 = b0 / bw;
+      bx = b0 - by0 * bw + j;
+      const bool wrap = bx >= bw;
+      bx = wrap ? bx - bw : bx;
+      by = by0 + (wrap ? 1 : 0);
+    } else {
+      by = b / bw;
+      bx = b - by * bw;
+    }
+    by = live ? by : 0;
+    bx = live ? bx : 0;
     const int x0 = bx * 8, y = by * 8 + r;
     const bool full = live && x0 + 8 <= W && by * 8 + 8 <= H;
     // a1: this lane's row (edge rows and columns repeat the last pixel)
