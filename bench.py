@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--pixels", type=float, default=0.0,
                     help="for --summarize-counters: pixels each launch codes (per-pixel rows)")
     ap.add_argument("--title", default="", help="for --summarize-counters: the table's heading")
-    ap.add_argument("--kernel", default="void dct::codec_kernel<dct::Recipe<10, 12, 12>, false>",
+    ap.add_argument("--kernel", default="void dct::rows::codec_rows_kernel<dct::Recipe<10, 12, 12>, false>",
                     help="kernel-name prefix for --summarize-profile")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "codec_kernel_8192.json"))
     return ap.parse_args()
@@ -169,9 +169,9 @@ def profile_markdown(d, row):
     tr, algo = d["traffic_bytes_per_dispatch"], d["algorithmic_bytes_per_dispatch"]
     waves = sq.get("SQ_WAVES", 0.0) or 1.0
     lines = [
-        f"# codec_kernel, {W} x {H} workload (recipe R(10, 12, 12), qs = {QS})", "",
+        f"# Fused codec kernel, {W} x {H} workload (recipe R(10, 12, 12), qs = {QS})", "",
         f"Fused codec kernel `{d['kernel']}` on one MI355X as `bench.py` runs it: five rotating "
-        f"{W} x {H} synthetic images, {W * H // 64:,} blocks per launch, one lane per block, "
+        f"{W} x {H} synthetic images, {W * H // 64:,} blocks per launch, "
         f"{int(waves):,} waves per launch.", "",
         f"Digest of the codec kernel's sources and flags when profiled: `{d['kernel_sha256']}`; `bench.py` "
         "reports the traffic below only while they still have this digest.", "",
@@ -210,10 +210,7 @@ def profile_markdown(d, row):
         f"| total | | | {tr / 1e6:.1f} MB |",
         f"| algorithmic (2 B/px) | | | {algo / 1e6:.1f} MB |", "",
         f"Traffic is {tr / algo:.3f} x the algorithmic bytes.  A plain copy's FETCH_SIZE reads half the "
-        "bytes it moves, hence the factor 2 on reads; writes need none.  The excess over the algorithmic "
-        "bytes: the register values the kernel's four-wave cap keeps in scratch (a few dozen bytes per "
-        "lane, written and read back once) and the SSE step's second read of each block's source bytes, "
-        "part of which misses L2.", "",
+        "bytes it moves, hence the factor 2 on reads; writes need none.", "",
         "## SQ counters per launch", "",
         "| counter | value | per wave |", "|---|---|---|",
     ]
@@ -223,9 +220,8 @@ def profile_markdown(d, row):
             per = "" if k in ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES") else f"{sq[k] / waves:.1f}"
             lines.append(f"| {k} | {sq[k]:.0f} | {per} |")
     if "SQ_INSTS_VALU" in sq:
-        per_wave = sq["SQ_INSTS_VALU"] / waves
-        lines += ["", f"Each lane codes one block, so a wave's {per_wave:.0f} VALU instructions are "
-                      f"{per_wave:.0f} per block, {per_wave / 64:.1f} per pixel, against the recipe's "
+        lines += ["", f"{sq['SQ_INSTS_VALU'] * 64 / (W * H):.1f} VALU lane-instructions per pixel "
+                      f"(SQ_INSTS_VALU x 64 / pixels), against the recipe's "
                       f"{OPS_PER_PIXEL:.0f} algorithmic operations per pixel.  "
                       f"SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU = "
                       f"{100 * sq.get('SQ_ACTIVE_INST_VALU2', 0) / sq['SQ_INSTS_VALU']:.1f}%: the share of VALU "
@@ -874,17 +870,17 @@ def bench_sweep(args):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / ((replays - 1) * reps)
         graph_ok = bool((sse[10:10 + reps] == sse[10]).all().item())
-        # the lane-per-row mapping (dct_codec_rows), eager calls from Python and a
-        # captured graph of its two launches per call (fill kernel and codec)
+        # the lane-per-block mapping (dct_codec_blocks): a captured graph of its two
+        # launches per call (fill kernel and codec)
         sse_r = torch.zeros(reps, dtype=torch.int64, device=dev)
         dst_r = codec.new_plane(w, h, dev)
-        codec.dct_codec_rows(src, QS, dst=dst_r, sse=sse_r[0:1])
+        codec.dct_codec_blocks(src, QS, dst=dst_r, sse=sse_r[0:1])
         torch.cuda.synchronize()
         graph_r = torch.cuda.CUDAGraph()
         with torch.cuda.stream(gstream):
             with torch.cuda.graph(graph_r, stream=gstream):
                 for i in range(reps):
-                    codec.dct_codec_rows(src, QS, dst=dst_r, sse=sse_r[i:i + 1])
+                    codec.dct_codec_blocks(src, QS, dst=dst_r, sse=sse_r[i:i + 1])
         torch.cuda.synchronize()
         graph_r.replay()
         torch.cuda.synchronize()
@@ -919,11 +915,11 @@ def bench_sweep(args):
         px = w * h
         rows.append({"W": w, "H": h, "gpu_ms": round(ms, 5), "gpu_gpx_s": round(px / ms / 1e6, 3),
                      "gpu_ms_eager_call": round(ms_eager, 5), "gpu_ms_with_copies": round(ms_copies, 5),
-                     "gpu_ms_lane_per_row": round(ms_rows, 5),
+                     "gpu_ms_lane_per_block": round(ms_rows, 5),
                      "cpu_oracle_ms_1core": round(1e3 * t1, 3), f"cpu_oracle_ms_{cores}cores": round(1e3 * tn, 3),
                      "psnr_db": round(codec.psnr_from_sse(osse, w, h), 6), "parity": parity,
                      "paper_cpu_ms": cpu_ms, "paper_gpu_ms": gpu_ms})
-        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.2f} us in a graph ({px / ms / 1e6:.1f} Gpx/s), lane per row "
+        print(f"[bench] sweep {w}x{h}: {ms * 1e3:.2f} us in a graph ({px / ms / 1e6:.1f} Gpx/s), lane per block "
               f"{ms_rows * 1e3:.2f} us, eager call "
               f"{ms_eager * 1e3:.1f} us, with copies "
               f"{ms_copies * 1e3:.1f} us, oracle 1 core {t1 * 1e3:.1f} ms", file=sys.stderr, flush=True)
@@ -935,9 +931,9 @@ def bench_sweep(args):
 
 def bench_mapping(args):
     """The two thread mappings of the fused codec on the 8192 x 8192 rotation:
-    one lane per block (dct_codec) against one lane per block row with LDS
-    transposes (dct_codec_rows).  Each is timed with HIP events over --steps
-    calls (fill kernel included for both) and checked against the other."""
+    one lane per block (dct_codec_blocks) against one lane per block row with LDS
+    transposes (dct_codec).  Each is timed with HIP events over --steps calls
+    (fill kernel included for both) and checked against the other."""
     import torch
 
     from paper_1306_1373_amd import codec
@@ -954,7 +950,7 @@ def bench_mapping(args):
         dsts.append(codec.new_plane(W, H, dev))
     out = {"workload": f"{W}x{H} rotation of {N_IMAGES} images, qs={QS}", "steps": args.steps}
     ref = None
-    for name, fn in (("lane_per_block", codec.dct_codec), ("lane_per_row_lds", codec.dct_codec_rows)):
+    for name, fn in (("lane_per_block", codec.dct_codec_blocks), ("lane_per_row_lds", codec.dct_codec)):
         sse = torch.zeros(args.warmup + args.steps, dtype=torch.int64, device=dev)
         for k in range(args.warmup):
             fn(srcs[k % N_IMAGES], QS, dst=dsts[k % N_IMAGES], sse=sse[k:k + 1])
@@ -1204,7 +1200,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
                      "peak": round(INT32_PEAK_TOPS, 2), "unit": "Tops/s",
                      "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": profiled_traffic(),
-                     "kernel": "codec_kernel<Recipe<10, 12, 12>, false>", "ops_per_pixel": OPS_PER_PIXEL,
+                     "kernel": "rows::codec_rows_kernel<Recipe<10, 12, 12>, false>",
+                     "ops_per_pixel": OPS_PER_PIXEL,
                      "avg_kernel_ms": round(ms_per_step, 5),
                      "timing": "HIP events on the launch stream around the timed steps, one kernel per step"},
         "deterministic": deterministic,

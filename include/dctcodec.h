@@ -163,14 +163,16 @@ DCT_API int dct_codec_accumulate(const uint8_t *src, int32_t W, int32_t H, int32
                                  uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev,
                                  void *stream);
 
-/* dct_codec computed with a second thread mapping: one lane per block row, the
- * row-to-column transposes staged through LDS (the shared-memory design of
- * Sec. 2.4), instead of one lane per block with the transpose done by register
- * renaming.  Bit-identical to dct_codec (arguments and outputs as dct_codec);
- * kept so that the two mappings can be measured against each other. */
-DCT_API int dct_codec_rows(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs,
-                           uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev,
-                           void *stream);
+/* dct_codec with the other thread mapping: one lane per 8x8 block, the block's
+ * 64 samples kept in that lane's registers through both passes, the
+ * row-to-column transpose a change of register index.  dct_codec and
+ * dct_codec_accumulate give each lane one block row and stage the transposes
+ * through LDS (the shared-memory design of Sec. 2.4); the recipe family and the
+ * batch use this mapping.  Bit-identical to dct_codec (arguments and outputs as
+ * dct_codec); kept so that the two mappings can be measured against each other. */
+DCT_API int dct_codec_blocks(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs,
+                             uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev,
+                             void *stream);
 
 /* Floating-point forms of the transform (the exact DCT of Sec. 2.5.1, eq. (6),
  * that Sec. 4.1 compares the Cordic-based codec against), for dct_forward_float

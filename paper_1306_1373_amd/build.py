@@ -53,11 +53,11 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-CODEC_KERNEL_FILES = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp")]
+CODEC_KERNEL_FILES = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp", "rows.hpp")]
 
 
 def codec_kernel_digest() -> str:
-    """SHA-256 over what the fused integer codec kernel is compiled from (its three
+    """SHA-256 over what the fused integer codec kernel is compiled from (its
     headers and the compiler flags): a profile of that kernel stays valid while
     this digest is unchanged, whatever else changes in the library."""
     import hashlib

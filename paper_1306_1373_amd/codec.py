@@ -40,7 +40,7 @@ _PROTOS = {
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dct_codec_accumulate": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                        C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "dct_codec_rows": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+    "dct_codec_blocks": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                  C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dct_forward_float": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_void_p, C.c_void_p]),
@@ -253,9 +253,9 @@ def dct_codec_accumulate(src, qs: int, sse, dst=None, qcoef=None, want_qcoef: bo
     return _codec(src, qs, dst, qcoef, sse, want_qcoef, "accumulate")
 
 
-def dct_codec_rows(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
-    """dct_codec with the lane-per-row, LDS-transpose mapping; returns as dct_codec."""
-    return _codec(src, qs, dst, qcoef, sse, want_qcoef, "rows")
+def dct_codec_blocks(src, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
+    """dct_codec with the lane-per-block mapping (the transpose in registers); returns as dct_codec."""
+    return _codec(src, qs, dst, qcoef, sse, want_qcoef, "blocks")
 
 
 def dct_codec_recipe(src, recipe, qs: int, dst=None, qcoef=None, sse=None, want_qcoef: bool = False):
@@ -283,9 +283,9 @@ def _codec(src, qs, dst, qcoef, sse, want_qcoef, recipe):
     if recipe is None:
         _check(load().dct_codec(p, W, H, s, int(qs), pd, ds, qptr, sse.data_ptr(), _stream(src)),
                "dct_codec")
-    elif recipe == "rows":
-        _check(load().dct_codec_rows(p, W, H, s, int(qs), pd, ds, qptr, sse.data_ptr(), _stream(src)),
-               "dct_codec_rows")
+    elif recipe == "blocks":
+        _check(load().dct_codec_blocks(p, W, H, s, int(qs), pd, ds, qptr, sse.data_ptr(), _stream(src)),
+               "dct_codec_blocks")
     elif recipe == "accumulate":
         if sse.dtype != torch.int64 or sse.numel() < 1 or not sse.is_cuda:
             raise TypeError("sse must be an int64 device tensor")

@@ -47,7 +47,31 @@ const RecipeEntry *find_recipe(int n, int F, int G) {
   return found;
 }
 
-// zero_sse: overwrite *sse_dev (dct_codec) rather than add to it (dct_codec_accumulate)
+// The default recipe with one lane per block row (rows.hpp), after zeroing the
+// SSE word unless zero_sse is false.
+int codec_rows(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+               int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream, bool zero_sse) {
+  if (int st = check_device(nullptr)) return st;
+  using RC = dct::DefaultRecipe;
+  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
+  const unsigned grid = dct::rows::launch_groups((nblocks + 7) / 8);
+  auto *sse = reinterpret_cast<unsigned long long *>(sse_dev);
+  hipStream_t s = as_stream(stream);
+  if (zero_sse) {
+    dct::fill_zero_kernel<<<1, 64, 0, s>>>(sse, 1);
+    if (launched()) return DCT_ERR_DEVICE;
+  }
+  const dct::CodecQuant qa = codec_quant(qs, RC::frac, RC::inv_frac);
+  if (qcoef_or_null)
+    dct::rows::codec_rows_kernel<RC, true><<<grid, dct::rows::kThreads, 0, s>>>(
+        src, W, H, src_stride, bw, nblocks, qa, dst, dst_stride, qcoef_or_null, sse);
+  else
+    dct::rows::codec_rows_kernel<RC, false><<<grid, dct::rows::kThreads, 0, s>>>(
+        src, W, H, src_stride, bw, nblocks, qa, dst, dst_stride, nullptr, sse);
+  return launched();
+}
+
+// The lane-per-block kernel under recipe rc; zero_sse: overwrite *sse_dev rather than add to it
 int codec_common(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, const RecipeEntry &rc, int32_t qs,
                  uint8_t *dst, int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream,
                  bool zero_sse = true) {
@@ -86,40 +110,21 @@ extern "C" {
 int dct_codec(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
               int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
   if (!codec_args_ok(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev)) return DCT_ERR_INVALID;
-  const RecipeEntry *rc = nullptr;
-  recipes_default(&rc);
-  return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream);
+  return codec_rows(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream, true);
 }
 
 int dct_codec_accumulate(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
                          int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
   if (!codec_args_ok(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev)) return DCT_ERR_INVALID;
-  const RecipeEntry *rc = nullptr;
-  recipes_default(&rc);
-  return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream, false);
+  return codec_rows(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream, false);
 }
 
-int dct_codec_rows(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
-                   int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
+int dct_codec_blocks(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t qs, uint8_t *dst,
+                     int32_t dst_stride, int16_t *qcoef_or_null, uint64_t *sse_dev, void *stream) {
   if (!codec_args_ok(src, W, H, src_stride, qs, dst, dst_stride, qcoef_or_null, sse_dev)) return DCT_ERR_INVALID;
-  if (int st = check_device(nullptr)) return st;
-  using RC = dct::DefaultRecipe;
-  const int bw = (W + 7) / 8, nblocks = bw * ((H + 7) / 8);
-  const int ngroups = (nblocks + 7) / 8;
-  const unsigned grid = static_cast<unsigned>(
-      std::min<int>((ngroups + 3) / 4, dct::rows::kMaxGroups));
-  auto *sse = reinterpret_cast<unsigned long long *>(sse_dev);
-  hipStream_t s = as_stream(stream);
-  dct::fill_zero_kernel<<<1, 64, 0, s>>>(sse, 1);
-  if (launched()) return DCT_ERR_DEVICE;
-  const dct::CodecQuant qa = codec_quant(qs, RC::frac, RC::inv_frac);
-  if (qcoef_or_null)
-    dct::rows::codec_rows_kernel<RC, true><<<grid, dct::rows::kThreads, 0, s>>>(
-        src, W, H, src_stride, bw, nblocks, qa, dst, dst_stride, qcoef_or_null, sse);
-  else
-    dct::rows::codec_rows_kernel<RC, false><<<grid, dct::rows::kThreads, 0, s>>>(
-        src, W, H, src_stride, bw, nblocks, qa, dst, dst_stride, nullptr, sse);
-  return launched();
+  const RecipeEntry *rc = nullptr;
+  recipes_default(&rc);
+  return codec_common(src, W, H, src_stride, *rc, qs, dst, dst_stride, qcoef_or_null, sse_dev, stream);
 }
 
 int dct_codec_recipe(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride, int32_t n_iter,

@@ -236,17 +236,15 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
     fused_apply_kernel<<<tiles, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, wq, wh, out, out_stride);
     return launched();
   }
-  // layer 1 and layer 4: one thread per kRows vertically adjacent pixels of a column
-  const int64_t ngroups = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * set.w;
-  layer1_kernel<<<px_grid(ngroups), kThreads, 0, s>>>(set, wq, a1, ngroups);
-  // tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image
+  // every layer in tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image
   const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
+  layer1_kernel<<<mgrid, kThreads, 0, s>>>(set, wq, wh, a1, ntiles);
   mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, nullptr, a2, npix, ntiles);
   mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, nullptr, a3, npix, ntiles);
-  const unsigned lgrid = static_cast<unsigned>(std::min<int64_t>((ngroups + kThreads - 1) / kThreads, kLossGroups));
-  layer4_kernel<true><<<lgrid, kThreads, 0, s>>>(set, a3, wq, ngroups, nullptr, 0, y, g4, sq,
-                                                 2.0f / static_cast<float>(npix), signal_scale(npix));
+  const unsigned lgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, kLossGroups));
+  layer4_kernel<<<lgrid, kThreads, 0, s>>>(set, a3, wq, wh, ntiles, y, g4, sq, 2.0f / static_cast<float>(npix),
+                                          signal_scale(npix));
   if (grad != nullptr) loss_reduce_kernel<<<1, kThreads, 0, s>>>(sq, static_cast<int>(lgrid), loss,
                                                                  1.0 / static_cast<double>(npix));
   return launched();

@@ -24,8 +24,10 @@
 // FP16's normal range for |y - t| between about 2^-22 and 2^7; the weight and
 // bias gradients are divided by S (exactly) when their partial sums are added.
 //
-// Kernels (one thread per pixel unless stated):
-//   layer1_kernel      x -> a1 (VALU, 288 FMA per pixel)
+// Kernels (a wave per tile of 3 rows x 16 pixels unless stated):
+//   layer1_kernel      x -> a1 on the matrix cores: the nine taps as the K of
+//                      v_mfma_f32_16x16x16_f16 over the decoded pixel values
+//                      0..255 (exact in FP16), the 1/255 and the bias after the sum
 //   mid_kernel<false>  a -> relu(conv(a)) for the 32 -> 32 layers on the matrix
 //                      cores: per wave, 16 pixels x 32 output channels, K = 9 taps
 //                      x 32 input channels as nine v_mfma_f32_16x16x32_f16 per
@@ -35,11 +37,13 @@
 //                      implicit GEMM with the layer's weights transposed (input
 //                      and output channels swapped) and the taps mirrored, and
 //                      the ReLU mask of a_l in place of bias and ReLU
-//   layer4_kernel      a3 -> y, and either the output pixel or the loss terms and
-//                      S dL/dy (training)
+//   layer4_kernel      a3 -> y (training), the loss terms and S dL/dy: the
+//                      32 -> 1 layer as the 32 -> 32 layers' GEMM with one
+//                      nonzero row of weights
 //   fused_apply_kernel inference in one launch: all four layers of a 28 x 26
 //                      output tile with x, a1, a2 and a3 held in LDS
-//   bwd4_kernel        g3 from dL/dy through layer 4 and the ReLU of a3 (VALU)
+//   bwd4_kernel        g3 from dL/dy through layer 4 and the ReLU of a3 (VALU,
+//                      one thread per pixel)
 //   wgrad_mid_kernel   weight and bias gradients of a 32 -> 32 layer as a GEMM
 //                      over pixels, K = 32 pixels of one image row per
 //                      instruction: three waves per workgroup, one per tap row
@@ -125,42 +129,123 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(const float *__restrict_
 // pixel rows a thread (layers 1 and 4) or a wave's tile (layers 2 and 3) computes
 inline constexpr int kRows = 3;
 
-// a1 = relu(conv(x; W1, b1))
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+// Layer 1 on the matrix cores, v_mfma_f32_16x16x16_f16 with the nine taps as K
+// (taps 9..15 zero): z[co] = sum_t W1[co][t] P[pixel + offset(t)] with P the
+// decoded pixel values 0..255 (exact in FP16, so every product is exact), then
+// a1 = relu(z / 255 + b1) from the FP32 sum.  Operands of output half m, lane
+// (i, g): A[i][4g+e] = W1[16m + i][4g + e], B[4g+e][i] = P of pixel i at tap
+// 4g + e, D[4g + r][i] = z[16m + 4g + r] of pixel i.
+struct L1Consts {
+  h4 wa[2];
+  float bv[2][4];
+};
+
+__device__ __forceinline__ void l1_consts(const _Float16 *__restrict__ wh, const float *__restrict__ wq,
+                                          L1Consts &c) {
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int t = 4 * g + e;
+      c.wa[m][e] = t < 9 ? wh[kW1 + (16 * m + i) * 9 + t] : static_cast<_Float16>(0.0f);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c.bv[m][r] = wq[kB1 + 16 * m + 4 * g + r];
+  }
+}
+
+// The lane's four channels 16m + 4g .. + 3 of a1 for its pixel, as two packed
+// words per half m, from the B operand bp (the pixel's taps 4g .. 4g + 3)
+__device__ __forceinline__ void l1_pixel(const L1Consts &c, h4 bp, uint2 (&out)[2]) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const f4 d = __builtin_amdgcn_mfma_f32_16x16x16f16(c.wa[m], bp, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    uint32_t hb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      hb[r] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(d[r] * kInv255 + c.bv[m][r], 0.0f)));
+    out[m] = make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+  }
+}
+
+// Layer 4 on the matrix cores: the 32 -> 1 convolution as nine
+// v_mfma_f32_16x16x32_f16 per tile row with the tap's weights in M-row 0 of A
+// (the other rows zero) and the same B operands as the 32 -> 32 layers: lane
+// (i, 0) ends with sum_t sum_ci W4[ci][t] a3[pixel i + offset(t)][ci] in element
+// 0 of its accumulator.
+struct L4Consts {
+  h8 wa[9];
+  float b4;
+};
+
+__device__ __forceinline__ void l4_consts(const _Float16 *__restrict__ wh, const float *__restrict__ wq,
+                                          L4Consts &c) {
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      c.wa[t][e] = i == 0 ? wh[kW4 + (8 * g + e) * 9 + t] : static_cast<_Float16>(0.0f);
+  c.b4 = wq[kB4];
+}
+
+// kRows tile rows of layer 4 (or of a 32 -> 32 layer's half m, with its weights
+// for wa): load(k, dx) gives the lane's B operand for input row k (0 ..
+// kRows + 1) and column offset dx; output row j uses input row k as tap row
+// k - j.  Shared by every kernel that forms these sums, so their order is the
+// same everywhere.
+template <class Load>
+__device__ __forceinline__ void l4_tile(const h8 (&wa)[9], Load load, f4 (&acc)[kRows]) {
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < kRows + 2; ++k)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const h8 bx = load(k, dx);
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const int dy = k - j;
+        if (dy >= 0 && dy <= 2) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[dy * 3 + dx], bx, acc[j], 0, 0, 0);
+      }
+    }
+}
+
+// a1 = relu(conv(x; W1, b1)): a wave computes kRows rows x 16 columns of one image
 __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const float *__restrict__ wq,
-                                                          _Float16 *__restrict__ a1, int64_t ngroups) {
-  // a thread computes kRows vertically adjacent pixels of one column: the
-  // (kRows + 2) x 3 neighbourhood is read and converted once for all of them
+                                                          const _Float16 *__restrict__ wh,
+                                                          _Float16 *__restrict__ a1, int64_t ntiles) {
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  L1Consts k1;
+  l1_consts(wh, wq, k1);
+  const uint32_t col_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
   const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
-  for (int64_t gidx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; gidx < ngroups;
-       gidx += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const uint32_t u = static_cast<uint32_t>(gidx);
-    const uint32_t col_id = u / static_cast<uint32_t>(s.w);
-    const int c = static_cast<int>(u - col_id * static_cast<uint32_t>(s.w));
-    const int b = static_cast<int>(col_id / row_groups);
-    const int r0 = static_cast<int>(col_id - static_cast<uint32_t>(b) * row_groups) * kRows;
-    float x[kRows + 2][3];
-#pragma unroll
-    for (int k = 0; k < kRows + 2; ++k)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) x[k][dx] = plane_px(s, s.plane, b, r0 - 1 + k, c + dx - 1) * kInv255;
+  const uint32_t step = gridDim.x * (kThreads / 64);
+  for (uint32_t tile = blockIdx.x * (kThreads / 64) + wave; tile < static_cast<uint32_t>(ntiles); tile += step) {
+    const uint32_t gid = tile / col_tiles;
+    const int b = static_cast<int>(gid / row_groups);
+    const int r0 = static_cast<int>(gid - static_cast<uint32_t>(b) * row_groups) * kRows;
+    const int c = static_cast<int>((tile - gid * col_tiles) * 16u) + i;
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
       const int r = r0 + j;
-      if (r >= s.h) break;
-      uint32_t words[kC / 2];
+      h4 bp;
 #pragma unroll
-      for (int co = 0; co < kC; ++co) {
-        float acc = wq[kB1 + co];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc += wq[kW1 + co * 9 + t] * x[j + t / 3][t % 3];
-        const uint32_t hbits = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc, 0.0f)));
-        words[co >> 1] = (co & 1) ? (words[co >> 1] | (hbits << 16)) : hbits;
+      for (int e = 0; e < 4; ++e) {
+        const int t = 4 * g + e;
+        bp[e] = static_cast<_Float16>(t < 9 ? plane_px(s, s.plane, b, r + t / 3 - 1, c + t % 3 - 1) : 0.0f);
       }
-      const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
-      uint4 *dst = reinterpret_cast<uint4 *>(a1 + p * kC);
+      uint2 out[2];
+      l1_pixel(k1, bp, out);
+      if (r < s.h && c < s.w) {
+        const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        dst[k] = make_uint4(words[4 * k], words[4 * k + 1], words[4 * k + 2], words[4 * k + 3]);
+        for (int m = 0; m < 2; ++m) *reinterpret_cast<uint2 *>(a1 + p * kC + 16 * m + 4 * g) = out[m];
+      }
     }
   }
 }
@@ -281,87 +366,67 @@ __device__ __forceinline__ float residual(float p, float net) {
   return p * kInv255 + net;
 }
 
-// y = x + conv(a3; W4, b4).  kTrain = false: writes the output pixel to `out`
-// (clamp(floor(255 y + 1/2))).  kTrain = true: y to y_out (if not null), the
-// scaled signal S dL/dy = fp16(fp32(grad_scale (y - t)) S) to g4, and the
-// workgroup's sum of (y - t)^2 to sq[blockIdx.x] (summed in a fixed order).  A
-// thread computes kRows vertically adjacent pixels of one column: each of the
-// kRows + 2 neighbour rows x 3 columns is loaded and converted once.
-template <bool kTrain>
+// Training forward of layer 4: y = x + conv(a3; W4, b4) on the matrix cores
+// (l4_tile, a wave per kRows rows x 16 columns of one image), then y to y_out
+// (if not null), the scaled signal S dL/dy = fp16(fp32(grad_scale (y - t)) S)
+// to g4, and the workgroup's sum of (y - t)^2 to sq[blockIdx.x] (summed in a
+// fixed order).
 __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Float16 *__restrict__ a3,
-                                                          const float *__restrict__ wq, int64_t ngroups,
-                                                          uint8_t *__restrict__ out, int out_stride,
+                                                          const float *__restrict__ wq,
+                                                          const _Float16 *__restrict__ wh, int64_t ntiles,
                                                           float *__restrict__ y_out, _Float16 *__restrict__ g4,
                                                           double *__restrict__ sq, float grad_scale, float S) {
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  L4Consts k4;
+  l4_consts(wh, wq, k4);
   double local = 0.0;
+  const uint32_t col_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
   const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
-  for (int64_t gidx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; gidx < ngroups;
-       gidx += static_cast<int64_t>(gridDim.x) * kThreads) {
-    // group id -> (image, row group, column)
-    const uint32_t u = static_cast<uint32_t>(gidx);
-    const uint32_t col_id = u / static_cast<uint32_t>(s.w);
-    const int c = static_cast<int>(u - col_id * static_cast<uint32_t>(s.w));
-    const int b = static_cast<int>(col_id / row_groups);
-    const int r0 = static_cast<int>(col_id - static_cast<uint32_t>(b) * row_groups) * kRows;
-    float acc[kRows];
-#pragma unroll
-    for (int j = 0; j < kRows; ++j) acc[j] = wq[kB4];
-#pragma unroll
-    for (int k = 0; k < kRows + 2; ++k) {  // input row r0 - 1 + k
-      const int rr = r0 - 1 + k;
-      if (rr < 0 || rr >= s.h) continue;
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int cc = c + dx - 1;
-        if (cc < 0 || cc >= s.w) continue;
-        const uint4 *src = reinterpret_cast<const uint4 *>(a3 + ((static_cast<int64_t>(b) * s.h + rr) * s.w + cc) * kC);
-        float av[kC];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const h8 hv = __builtin_bit_cast(h8, src[q]);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) av[8 * q + e] = static_cast<float>(hv[e]);
-        }
-#pragma unroll
-        for (int j = 0; j < kRows; ++j) {
-          const int dy = k - j;  // tap row of output row r0 + j
-          if (dy >= 0 && dy <= 2) {
-#pragma unroll
-            for (int ci = 0; ci < kC; ++ci) acc[j] += wq[kW4 + ci * 9 + dy * 3 + dx] * av[ci];
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kRows; ++j) {
-      const int r = r0 + j;
-      if (r >= s.h) break;
-      const float y = residual(plane_px(s, s.plane, b, r, c), acc[j]);
-      const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
-      if constexpr (!kTrain) {
-        const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
-        out[static_cast<size_t>(r) * out_stride + c] = static_cast<uint8_t>(v);
+  const uint32_t step = gridDim.x * (kThreads / 64);
+  for (uint32_t tile = blockIdx.x * (kThreads / 64) + wave; tile < static_cast<uint32_t>(ntiles); tile += step) {
+    const uint32_t gid = tile / col_tiles;
+    const int b = static_cast<int>(gid / row_groups);
+    const int r0 = static_cast<int>(gid - static_cast<uint32_t>(b) * row_groups) * kRows;
+    const int c = static_cast<int>((tile - gid * col_tiles) * 16u) + i;
+    f4 acc[kRows];
+    l4_tile(k4.wa, [&](int k, int dx) {
+      const int rr = r0 - 1 + k, cc = c + dx - 1;
+      h8 bx;
+      if (rr >= 0 && rr < s.h && cc >= 0 && cc < s.w && c < s.w) {
+        bx = *reinterpret_cast<const h8 *>(a3 + ((static_cast<int64_t>(b) * s.h + rr) * s.w + cc) * kC + 8 * g);
       } else {
-        const float e = y - plane_px(s, s.orig, b, r, c) * kInv255;
-        if (y_out) y_out[p] = y;
-        const float gv = grad_scale * e;
-        g4[p] = static_cast<_Float16>(gv * S);
-        local += static_cast<double>(e) * e;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bx[e] = static_cast<_Float16>(0.0f);
+      }
+      return bx;
+    }, acc);
+    if (g == 0 && c < s.w) {
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const int r = r0 + j;
+        if (r < s.h) {
+          const float y = residual(plane_px(s, s.plane, b, r, c), acc[j][0] + k4.b4);
+          const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
+          const float e = y - plane_px(s, s.orig, b, r, c) * kInv255;
+          if (y_out) y_out[p] = y;
+          const float gv = grad_scale * e;
+          g4[p] = static_cast<_Float16>(gv * S);
+          local += static_cast<double>(e) * e;
+        }
       }
     }
   }
-  if constexpr (kTrain) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, 64);
-    __shared__ double wsum[kThreads / 64];
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
+  for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, 64);
+  __shared__ double wsum[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
-      sq[blockIdx.x] = t;
-    }
+    for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
+    sq[blockIdx.x] = t;
   }
 }
 
@@ -618,39 +683,51 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 //
 // A workgroup of kFThreads threads computes an output tile of kTW x kTH pixels
 // of one image.  Each layer is computed on the region the next one reads (one
-// pixel more on every side), so the tile's x, a1, a2 and a3 never leave LDS and
-// only the decoded and the output pixels touch HBM.  Positions outside the image
-// hold zeros at every layer (the network's zero padding).  Every float is
-// computed as in layer1_kernel, mid_kernel<false> and layer4_kernel (same
-// operands, same order of the sums, the same roundings of x = p / 255 and of
-// y), so the output is the rounding of the y those kernels form.
+// pixel more on every side), so the tile's decoded pixels, a1, a2 and a3 never
+// leave LDS and only the decoded and the output pixels touch HBM.  Positions
+// outside the image hold zeros at every layer (the network's zero padding).
+// Every layer runs on the matrix cores through the same functions as the
+// one-layer kernels of the training pass (l1_pixel, mid tiles, l4_tile), with
+// the same operands in the same order, so the output is the rounding of the y
+// those kernels form.
 //
 // Regions, in rows and columns relative to the tile's top-left output pixel:
 //   a3  rows -1 .. 3 kG3 - 2, columns -1 .. 30  (kG3 row groups x two 16-column halves)
 //   a2  rows -2 .. 3 kG2 - 3, columns -2 .. 31  (kG2 groups x two halves; columns 30, 31
 //       are read only by a3 columns past the tile and are never written)
-//   a1  rows -3 .. 3 kG2 - 2, columns -3 .. 30  (one thread per column and three rows)
-//   x   rows -4 .. 3 kG2 - 1, columns -4 .. 31
+//   a1  rows -3 .. 3 kG1 - 4, columns -3 .. 30  (kG1 groups x three 16-column thirds, the
+//       last cut at column 30)
+//   P   rows -4 .., columns -4 .. 31 (the decoded pixels, FP16)
+//
+// Activations are stored pixel-major, 64 bytes per pixel, its four 16-byte
+// channel groups G permuted within the pixel to slot G ^ ((q >> 2) & 3) for the
+// pixel's index q in its region: the eight lanes that one 16-byte LDS access
+// serves read consecutive pixels, and their groups then fall in eight
+// different 16-byte bank ranges.
 inline constexpr int kTW = 28;                          // output columns of a tile
 inline constexpr int kTH = 26;                          // output rows of a tile
 inline constexpr int kFThreads = 512;                   // eight waves
 inline constexpr int kG3 = (kTH + 2 + kRows - 1) / kRows;      // a3 row groups
 inline constexpr int kG2 = (3 * kG3 + 2 + kRows - 1) / kRows;  // a2 row groups (cover a3's rows +- 1)
-inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = kR2 + 2, kRX = kR1 + 2;  // rows held
-inline constexpr int kC3 = 32, kC2 = 34, kC1 = 34, kCX = 36;                      // columns held
+inline constexpr int kG1 = (3 * kG2 + 2 + kRows - 1) / kRows;  // a1 row groups (cover a2's rows +- 1)
+inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = 3 * kG1, kRX = kR1 + 2;  // rows held
+inline constexpr int kC3 = 32, kC2 = 34, kC1 = 34, kCX = 36;                     // columns held
 inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; a3 later reuses this space
 inline constexpr int kLdsA2 = kR2 * kC2 * kC * 2;
-inline constexpr int kLdsX = kRX * kCX * 4;
+inline constexpr int kLdsX = kRX * kCX * 2;
 static_assert(kR3 * kC3 * kC * 2 <= kLdsA1, "a3 fits in a1's space");
 static_assert(kLdsA1 + kLdsA2 + kLdsX <= 160 * 1024, "the tile fits in one CU's LDS");
 
-// relu(conv(ain; W, b)) on a 16-pixel x kRows tile of a 32 -> 32 layer, operands
-// from LDS.  `ain` holds a region of cin columns whose column 0 is one to the
-// left of this tile's column 0 and whose row 0 is one above its row 0; the tile
-// writes rows 0 .. kRows - 1 and columns i of `aout` (cout columns per row),
-// zero where the image position (img_r0 + j, img_c0 + i) lies outside the image.
-__device__ __forceinline__ void fused_mid_tile(const _Float16 *ain, int cin, int rin0, int cin0,
-                                               const h8 (&wa)[9][2], const float (&bv)[2][4], _Float16 *aout,
+// byte offset of channel group G of pixel q (index in its region)
+__device__ __forceinline__ int act_slot(int q, int G) { return (q * 4 + (G ^ ((q >> 2) & 3))) * 16; }
+
+// 32 -> 32 layer on a 16-pixel x kRows tile, operands from LDS: `ain` holds a
+// region of cin columns whose column 0 is one to the left of this tile's column
+// 0 and whose row 0 is one above its row 0 (rin0 rows down); the tile writes
+// rows rout0 .. + kRows - 1, columns cout0 + i of `aout` (cout columns), zero where
+// the image position (img_r0 + j, img_c0 + i) lies outside the image.
+__device__ __forceinline__ void fused_mid_tile(const uint8_t *ain, int cin, int rin0, int cin0,
+                                               const h8 (&wa)[9][2], const float (&bv)[2][4], uint8_t *aout,
                                                int cout, int rout0, int cout0, int img_r0, int img_c0, int H,
                                                int W) {
   const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
@@ -661,7 +738,7 @@ __device__ __forceinline__ void fused_mid_tile(const _Float16 *ain, int cin, int
   for (int k = 0; k < kRows + 2; ++k) {  // input row (rin0 + k), image row img_r0 - 1 + k
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const h8 bx = *reinterpret_cast<const h8 *>(ain + ((rin0 + k) * cin + cin0 + i + dx) * kC + 8 * g);
+      const h8 bx = *reinterpret_cast<const h8 *>(ain + act_slot((rin0 + k) * cin + cin0 + i + dx, g));
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         const int dy = k - j;
@@ -678,13 +755,14 @@ __device__ __forceinline__ void fused_mid_tile(const _Float16 *ain, int cin, int
   for (int j = 0; j < kRows; ++j) {
     const int r = img_r0 + j;
     const bool in = r >= 0 && r < H && c >= 0 && c < W;
+    const int q = (rout0 + j) * cout + cout0 + i;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       uint32_t hb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        hb[q] = in ? __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][q] + bv[m][q], 0.0f))) : 0u;
-      *reinterpret_cast<uint2 *>(aout + ((rout0 + j) * cout + cout0 + i) * kC + 16 * m + 4 * g) =
+      for (int t = 0; t < 4; ++t)
+        hb[t] = in ? __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][t] + bv[m][t], 0.0f))) : 0u;
+      *reinterpret_cast<uint2 *>(aout + act_slot(q, 2 * m + (g >> 1)) + 8 * (g & 1)) =
           make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
     }
   }
@@ -711,54 +789,53 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
                                                                 const _Float16 *__restrict__ wh,
                                                                 uint8_t *__restrict__ out, int out_stride) {
   extern __shared__ __align__(16) uint8_t lds[];
-  _Float16 *a1 = reinterpret_cast<_Float16 *>(lds);
-  _Float16 *a3 = a1;  // a1 is dead once a2 is formed
-  _Float16 *a2 = reinterpret_cast<_Float16 *>(lds + kLdsA1);
-  float *xs = reinterpret_cast<float *>(lds + kLdsA1 + kLdsA2);
+  uint8_t *a1 = lds;
+  uint8_t *a3 = lds;  // a1 is dead once a2 is formed
+  uint8_t *a2 = lds + kLdsA1;
+  _Float16 *xs = reinterpret_cast<_Float16 *>(lds + kLdsA1 + kLdsA2);
   const int tiles_x = (W + kTW - 1) / kTW;
   const int R0 = static_cast<int>(blockIdx.x) / tiles_x * kTH, C0 = static_cast<int>(blockIdx.x) % tiles_x * kTW;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // the decoded pixels p (as floats) on rows R0 - 4 .., columns C0 - 4 .., zero
-  // outside the image; x = p / 255 is formed where it is used, as in the
-  // one-layer kernels
+  const int l = tid & 63, i = l & 15, g = l >> 4;
+  // the decoded pixels P on rows R0 - 4 .., columns C0 - 4 .., zero outside the image
   for (int k = tid; k < kRX * kCX; k += kFThreads) {
     const int rr = R0 - 4 + k / kCX, cc = C0 - 4 + k % kCX;
-    xs[k] = rr >= 0 && rr < H && cc >= 0 && cc < W ? static_cast<float>(plane[static_cast<size_t>(rr) * stride + cc])
-                                                   : 0.0f;
+    xs[k] = static_cast<_Float16>(rr >= 0 && rr < H && cc >= 0 && cc < W
+                                      ? static_cast<float>(plane[static_cast<size_t>(rr) * stride + cc])
+                                      : 0.0f);
   }
   __syncthreads();
-  // layer 1 on rows -3 .. kR1 - 4, columns -3 .. 30: one thread per column and kRows rows
-  constexpr int kG1 = (kR1 + kRows - 1) / kRows;
-  for (int k = tid; k < kG1 * kC1; k += kFThreads) {
-    const int col = k % kC1, r0 = k / kC1 * kRows;  // region coordinates (row 0 = image row R0 - 3)
-    float x[kRows + 2][3];
+  {
+    // layer 1: a1 rows -3 .., columns -3 .. 30 (region row 0 = image row R0 - 3,
+    // column 0 = C0 - 3; P region row 0 = image row R0 - 4)
+    L1Consts k1;
+    l1_consts(wh, wq, k1);
+    for (int task = wave; task < kG1 * 3; task += kFThreads / 64) {
+      const int grp = task / 3, third = task - grp * 3;
+      const int col = 16 * third + i;
 #pragma unroll
-    for (int q = 0; q < kRows + 2; ++q)
+      for (int j = 0; j < kRows; ++j) {
+        const int rr = grp * kRows + j;
+        h4 bp;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int xr = r0 + q, xc = col + dx;  // x region: row 0 = image row R0 - 4
-        x[q][dx] = (xr < kRX ? xs[xr * kCX + xc] : 0.0f) * kInv255;
+        for (int e = 0; e < 4; ++e) {
+          const int t = 4 * g + e;
+          // tap (t / 3, t % 3) of a1 region (rr, col) is P region (rr + t / 3, col + t % 3)
+          bp[e] = t < 9 && col < kC1 ? xs[(rr + t / 3) * kCX + col + t % 3] : static_cast<_Float16>(0.0f);
+        }
+        uint2 o[2];
+        l1_pixel(k1, bp, o);
+        if (col < kC1) {
+          const int ir = R0 - 3 + rr, ic = C0 - 3 + col;
+          const bool in = ir >= 0 && ir < H && ic >= 0 && ic < W;
+          const int q = rr * kC1 + col;
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+            *reinterpret_cast<uint2 *>(a1 + act_slot(q, 2 * m + (g >> 1)) + 8 * (g & 1)) =
+                in ? o[m] : make_uint2(0u, 0u);
+        }
       }
-#pragma unroll
-    for (int j = 0; j < kRows; ++j) {
-      const int rr = r0 + j;
-      if (rr >= kR1) break;
-      const int ir = R0 - 3 + rr, ic = C0 - 3 + col;
-      const bool in = ir >= 0 && ir < H && ic >= 0 && ic < W;
-      uint32_t words[kC / 2];
-#pragma unroll
-      for (int co = 0; co < kC; ++co) {
-        float acc = wq[kB1 + co];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc += wq[kW1 + co * 9 + t] * x[j + t / 3][t % 3];
-        const uint32_t hbits = in ? __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc, 0.0f))) : 0u;
-        words[co >> 1] = (co & 1) ? (words[co >> 1] | (hbits << 16)) : hbits;
-      }
-      uint4 *dst = reinterpret_cast<uint4 *>(a1 + (rr * kC1 + col) * kC);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        dst[q] = make_uint4(words[4 * q], words[4 * q + 1], words[4 * q + 2], words[4 * q + 3]);
     }
   }
   __syncthreads();
@@ -786,48 +863,31 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
     }
   }
   __syncthreads();
-  // layer 4 on the tile's pixels: one thread per column and kRows rows
-  constexpr int kG4 = (kTH + kRows - 1) / kRows;
-  for (int k = tid; k < kG4 * kTW; k += kFThreads) {
-    const int col = k % kTW, r0 = k / kTW * kRows;
-    const int c = C0 + col;
-    if (c >= W || R0 + r0 >= H) continue;
-    float acc[kRows];
-#pragma unroll
-    for (int j = 0; j < kRows; ++j) acc[j] = wq[kB4];
-#pragma unroll
-    for (int q = 0; q < kRows + 2; ++q) {  // image row R0 + r0 - 1 + q, a3 region row r0 + q
-      const int rr = R0 + r0 - 1 + q;
-      if (rr < 0 || rr >= H) continue;
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int cc = c + dx - 1;
-        if (cc < 0 || cc >= W) continue;
-        const uint4 *src = reinterpret_cast<const uint4 *>(a3 + ((r0 + q) * kC3 + col + dx) * kC);
-        float av[kC];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const h8 hv = __builtin_bit_cast(h8, src[u]);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) av[8 * u + e] = static_cast<float>(hv[e]);
-        }
+  {
+    // layer 4 on the tile's pixels (a3 region row 0 = image row R0 - 1, column 0 = C0 - 1)
+    L4Consts k4;
+    l4_consts(wh, wq, k4);
+    constexpr int kG4 = (kTH + kRows - 1) / kRows;
+    for (int task = wave; task < kG4 * 2; task += kFThreads / 64) {
+      const int grp = task >> 1, half = task & 1;
+      const int r0 = grp * kRows, col = 16 * half + i;  // output tile coordinates
+      f4 acc[kRows];
+      l4_tile(k4.wa, [&](int k, int dx) {
+        // input row k is a3 region row r0 + k, column offset dx is a3 region column col + dx
+        return *reinterpret_cast<const h8 *>(a3 + act_slot((r0 + k) * kC3 + col + dx, g));
+      }, acc);
+      const int c = C0 + col;
+      if (g == 0 && col < kTW && c < W) {
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
-          const int dy = q - j;
-          if (dy >= 0 && dy <= 2) {
-#pragma unroll
-            for (int ci = 0; ci < kC; ++ci) acc[j] += wq[kW4 + ci * 9 + dy * 3 + dx] * av[ci];
+          const int r = R0 + r0 + j;
+          if (r0 + j < kTH && r < H) {
+            const float y = residual(static_cast<float>(xs[(r0 + j + 4) * kCX + col + 4]), acc[j][0] + k4.b4);
+            const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
+            out[static_cast<size_t>(r) * out_stride + c] = static_cast<uint8_t>(v);
           }
         }
       }
-    }
-#pragma unroll
-    for (int j = 0; j < kRows; ++j) {
-      const int r = R0 + r0 + j;
-      if (r0 + j >= kTH || r >= H) break;
-      const float y = residual(xs[(r0 + j + 4) * kCX + col + 4], acc[j]);
-      const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
-      out[static_cast<size_t>(r) * out_stride + c] = static_cast<uint8_t>(v);
     }
   }
 }

@@ -1,6 +1,8 @@
 // rows.hpp -- the fused codec with one lane per block row and the row-to-column
 // transposes staged through LDS (the mapping of the paper's Sec. 2.4 shared-
-// memory design), measured against the lane-per-block kernel of kernels.hpp.
+// memory design): the kernel of dct_codec and dct_codec_accumulate.  The
+// lane-per-block kernel of kernels.hpp, which keeps a block in one lane's
+// registers, serves the recipe family, the batch and dct_codec_blocks.
 //
 // A wave codes eight horizontally consecutive blocks; lane (j, r) = (lane % 8,
 // lane / 8) owns row r of block j for the row passes and column r of block j
@@ -92,7 +94,17 @@ __device__ __forceinline__ void inverse_line(int (&z)[8]) {
 }
 
 inline constexpr int kThreads = 256;               // four waves
-inline constexpr int kMaxGroups = 8192;            // workgroups at most (waves loop over further groups)
+
+// Workgroups of a launch over ngroups groups of eight blocks.  A wave that codes
+// one group spends much of its life starting up, so waves take four groups
+// each once the image is large enough to fill the device that way; smaller images
+// give each wave one group (their time is one wave's latency).  Measured at
+// 8192 x 8192: one group per wave 245 us, four 143 us, sixteen 145 us.
+inline unsigned launch_groups(int ngroups) {
+  const int one = (ngroups + 3) / 4, four = (ngroups + 15) / 16;
+  if (one <= 1024) return static_cast<unsigned>(one);
+  return static_cast<unsigned>(four > 8192 ? 8192 : (four < 1024 ? 1024 : four));
+}
 // LDS layout of a wave's tile: element (a, b) of block j (a the pass's output
 // index, b the line) at word 72 j + 9 a + b.  A row-pass store (fixed a, lanes
 // (j, b)) hits words 8 j + b + 9 a (mod 64) and a column-pass load (fixed b, lanes

@@ -261,18 +261,25 @@ def signal_scale(n):
 
 def emulate(p, x, t, g16=True, scale=None):
     """The network's forward and backward pass in the GPU's arithmetic: FP32
-    products and sums (BLAS order), activations stored as FP16, backward signals
+    products and sums (BLAS order; layer 1 on the pixel values 0..255, scaled by
+    1/255 after the sum), activations stored as FP16, backward signals
     rounded to FP16 after multiplying by `scale` (default: the GPU's, from the
     batch's pixel count) when g16.  Returns (y, grad)."""
     f32, f16 = np.float32, np.float16
     L = [(w.astype(f32), b.astype(f32)) for w, b in layers(p)]
     inv = f32(1.0) / f32(255.0)
-    xp = (np.asarray(x, np.float64) * 255.0).round().astype(f32)[None] * inv
+    P = (np.asarray(x, np.float64) * 255.0).round().astype(f32)[None]
+    xp = P * inv
     tt = (np.asarray(t, np.float64) * 255.0).round().astype(f32)[None] * inv
     a = [xp]
     z = []
     for l, (w, b) in enumerate(L):
-        zz = conv(a[-1], w, b).astype(f32)
+        if l == 0:     # the pixel values 0..255 (exact) against the weights, then 1/255 and the bias
+            zz = (conv(P, w).astype(f32) * inv + b[:, None, None, None]).astype(f32)
+        elif l == 3:   # the sums of the matrix cores, then the bias
+            zz = (conv(a[-1], w).astype(f32) + b[:, None, None, None]).astype(f32)
+        else:
+            zz = conv(a[-1], w, b).astype(f32)
         z.append(zz)
         if l < 3:
             a.append(np.maximum(zz, f32(0)).astype(f16).astype(f32))

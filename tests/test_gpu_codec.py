@@ -274,11 +274,13 @@ def test_accumulate_over_bands(hip, oracle_mod, torch_mod):
 
 @pytest.mark.parametrize("W,H,qs", [(512, 512, 4), (1, 1, 4), (13, 5, 2), (1024, 814, 8), (333, 97, 16),
                                     (2048, 1536, 4)])
-def test_row_mapping_bit_exact(hip, oracle_mod, W, H, qs):
-    # the lane-per-row codec (LDS transposes) against the oracle, with padded strides
+def test_block_mapping_bit_exact(hip, oracle_mod, W, H, qs):
+    # the lane-per-block codec (transpose in registers) against the oracle, with
+    # padded strides; dct_codec itself (one lane per block row) is checked by
+    # every other test here
     img = synth(W, H, 40 + W % 7)
     src = to_dev(img, stride=((W + 7) // 8) * 8 + 16)
-    dst, sse, q = hip.dct_codec_rows(src, qs, want_qcoef=True)
+    dst, sse, q = hip.dct_codec_blocks(src, qs, want_qcoef=True)
     rec, osse, oq = oracle_mod.cordic_codec(img, qs, want_q=True)
     assert int(host(sse)[0]) == osse
     assert np.array_equal(host(q), oq)
@@ -313,11 +315,12 @@ def test_full_size_8192(hip, oracle_mod):
     assert sse_h == osse
     assert np.array_equal(q_h, oq)
     assert np.array_equal(rec_h, orec)
-    say("[gpu] 8192x8192 fused codec, lane-per-row mapping")
-    d_rows, s_rows = hip.dct_codec_rows(src, 4)
-    assert int(host(s_rows)[0]) == osse
-    assert np.array_equal(host(d_rows), orec)
-    del d_rows
+    say("[gpu] 8192x8192 fused codec, lane-per-block mapping")
+    d_blk, s_blk, q_blk = hip.dct_codec_blocks(src, 4, want_qcoef=True)
+    assert int(host(s_blk)[0]) == osse
+    assert np.array_equal(host(d_blk), orec)
+    assert np.array_equal(host(q_blk), oq)
+    del d_blk, q_blk
     say("[gpu] 8192x8192 fused codec, accumulating entry point (the benchmark's)")
     import torch
     acc = torch.zeros(1, dtype=torch.int64, device="cuda")
