@@ -29,7 +29,7 @@ constexpr int kEdgeChunks = 16;
 constexpr int kLossGroups = 1024;
 
 struct DeblockLayout {
-  size_t wq, wh, sq, a1, a2, a3, g4, ga, gb, part, bytes;
+  size_t wq, wh, ops, sq, a1, a2, a3, g4, ga, gb, part, bytes;
 };
 DeblockLayout deblock_layout(int64_t npix, bool training);
 int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *params, uint8_t *ws,
@@ -176,6 +176,8 @@ DeblockLayout deblock_layout(int64_t npix, bool training) {
   o += align256(sizeof(float) * dct::db::kNParam);
   L.wh = o;
   o += align256(sizeof(_Float16) * dct::db::kNParam);
+  L.ops = o;
+  if (!training) o += align256(sizeof(dct::db::WeightOps));
   L.sq = o;
   o += align256(sizeof(double) * kLossGroups);
   const size_t act = align256(sizeof(_Float16) * dct::db::kC * static_cast<size_t>(npix));
@@ -232,8 +234,10 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
         hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_apply_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (attr != hipSuccess) return DCT_ERR_DEVICE;
+    auto *ops = reinterpret_cast<WeightOps *>(ws + L.ops);
+    prep_ops_kernel<<<grid_for(kPrepOpsThreads), kThreads, 0, s>>>(wh, ops);
     const unsigned tiles = static_cast<unsigned>(((set.w + kTW - 1) / kTW) * ((set.h + kTH - 1) / kTH));
-    fused_apply_kernel<<<tiles, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, wq, wh, out, out_stride);
+    fused_apply_kernel<<<tiles, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, wq, ops, out, out_stride);
     return launched();
   }
   // every layer in tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image

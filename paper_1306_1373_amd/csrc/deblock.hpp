@@ -126,8 +126,51 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(const float *__restrict_
   }
 }
 
-// pixel rows a thread (layers 1 and 4) or a wave's tile (layers 2 and 3) computes
+// pixel rows a wave's tile computes
 inline constexpr int kRows = 3;
+
+// The matrix-core A operands of every lane, laid out so that a lane loads its
+// whole set with 16-byte accesses, consecutive lanes at consecutive addresses
+// (prepared once per call from the FP16 weights):
+//   mid[layer][m][t][lane]  layers 2 and 3: W[16m + i][8g + e][t], e = 0..7
+//   l4[t][lane]             layer 4: W4[8g + e][t] in lane i = 0, zero elsewhere
+//   l1[m][lane]             layer 1: W1[16m + i][4g + e], e = 0..3 (taps 9.. zero)
+struct WeightOps {
+  h8 mid[2][2][9][64];
+  h8 l4[9][64];
+  _Float16 l1[2][64][4];
+};
+
+__global__ __launch_bounds__(kThreads) void prep_ops_kernel(const _Float16 *__restrict__ wh, WeightOps *__restrict__ ops) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;  // one thread per 16-byte operand slot
+  constexpr int kMid = 2 * 2 * 9 * 64, kL4 = 9 * 64, kL1 = 2 * 64;
+  const _Float16 zero = static_cast<_Float16>(0.0f);
+  if (k < kMid) {
+    const int lane = k % 64, t = (k / 64) % 9, m = (k / (64 * 9)) % 2, layer = k / (64 * 9 * 2);
+    const int i = lane & 15, g = lane >> 4;
+    const _Float16 *w = wh + (layer == 0 ? kW2 : kW3);
+    h8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = w[((16 * m + i) * kC + 8 * g + e) * 9 + t];
+    ops->mid[layer][m][t][lane] = v;
+  } else if (k < kMid + kL4) {
+    const int lane = (k - kMid) % 64, t = (k - kMid) / 64;
+    const int i = lane & 15, g = lane >> 4;
+    h8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = i == 0 ? wh[kW4 + (8 * g + e) * 9 + t] : zero;
+    ops->l4[t][lane] = v;
+  } else if (k < kMid + kL4 + kL1) {
+    const int lane = (k - kMid - kL4) % 64, m = (k - kMid - kL4) / 64;
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int t = 4 * g + e;
+      ops->l1[m][lane][e] = t < 9 ? wh[kW1 + (16 * m + i) * 9 + t] : zero;
+    }
+  }
+}
+inline constexpr int kPrepOpsThreads = 2 * 2 * 9 * 64 + 9 * 64 + 2 * 64;
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
@@ -768,25 +811,25 @@ __device__ __forceinline__ void fused_mid_tile(const uint8_t *ain, int cin, int 
   }
 }
 
-__device__ __forceinline__ void load_mid_weights(const _Float16 *__restrict__ wh_layer, const float *__restrict__ bias,
-                                                 h8 (&wa)[9][2], float (&bv)[2][4]) {
-  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+// a mid layer's A operands (layer 0: W2, 1: W3) and biases for this lane
+__device__ __forceinline__ void load_mid_ops(const WeightOps *__restrict__ ops, int layer,
+                                             const float *__restrict__ bias, h8 (&wa)[9][2], float (&bv)[2][4]) {
+  const int l = threadIdx.x & 63, g = l >> 4;
 #pragma unroll
   for (int t = 0; t < 9; ++t)
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) wa[t][m][e] = wh_layer[((16 * m + i) * kC + 8 * g + e) * 9 + t];
+    for (int m = 0; m < 2; ++m) wa[t][m] = ops->mid[layer][m][t][l];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r) bv[m][r] = bias[16 * m + 4 * g + r];
 }
 
-// The deblocked output plane of one decoded plane (W x H, pitch stride), tile by tile.
+// The deblocked output plane of one decoded plane (W x H, pitch stride), tile by
+// tile.  Each layer's weights are loaded while the layer before it computes.
 __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *__restrict__ plane, int W, int H,
                                                                 int stride, const float *__restrict__ wq,
-                                                                const _Float16 *__restrict__ wh,
+                                                                const WeightOps *__restrict__ ops,
                                                                 uint8_t *__restrict__ out, int out_stride) {
   extern __shared__ __align__(16) uint8_t lds[];
   uint8_t *a1 = lds;
@@ -798,6 +841,16 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l = tid & 63, i = l & 15, g = l >> 4;
+  L1Consts k1;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    k1.wa[m] = *reinterpret_cast<const h4 *>(ops->l1[m][l]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) k1.bv[m][r] = wq[kB1 + 16 * m + 4 * g + r];
+  }
+  h8 wa2[9][2];
+  float bv2[2][4];
+  load_mid_ops(ops, 0, wq + kB2, wa2, bv2);
   // the decoded pixels P on rows R0 - 4 .., columns C0 - 4 .., zero outside the image
   for (int k = tid; k < kRX * kCX; k += kFThreads) {
     const int rr = R0 - 4 + k / kCX, cc = C0 - 4 + k % kCX;
@@ -809,8 +862,6 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
   {
     // layer 1: a1 rows -3 .., columns -3 .. 30 (region row 0 = image row R0 - 3,
     // column 0 = C0 - 3; P region row 0 = image row R0 - 4)
-    L1Consts k1;
-    l1_consts(wh, wq, k1);
     for (int task = wave; task < kG1 * 3; task += kFThreads / 64) {
       const int grp = task / 3, third = task - grp * 3;
       const int col = 16 * third + i;
@@ -839,34 +890,29 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
     }
   }
   __syncthreads();
-  {
-    // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (region row 0 = image row R0 - 3, column 0 = C0 - 3)
-    h8 wa[9][2];
-    float bv[2][4];
-    load_mid_weights(wh + kW2, wq + kB2, wa, bv);
-    for (int task = wave; task < kG2 * 2; task += kFThreads / 64) {
-      const int grp = task >> 1, half = task & 1;
-      const int ro = grp * kRows;  // a2 region row (row 0 = image row R0 - 2)
-      fused_mid_tile(a1, kC1, ro, 16 * half, wa, bv, a2, kC2, ro, 16 * half, R0 - 2 + ro, C0 - 2 + 16 * half, H, W);
-    }
+  h8 wa3[9][2];
+  float bv3[2][4];
+  load_mid_ops(ops, 1, wq + kB3, wa3, bv3);
+  // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (region row 0 = image row R0 - 3, column 0 = C0 - 3)
+  for (int task = wave; task < kG2 * 2; task += kFThreads / 64) {
+    const int grp = task >> 1, half = task & 1;
+    const int ro = grp * kRows;  // a2 region row (row 0 = image row R0 - 2)
+    fused_mid_tile(a1, kC1, ro, 16 * half, wa2, bv2, a2, kC2, ro, 16 * half, R0 - 2 + ro, C0 - 2 + 16 * half, H, W);
   }
   __syncthreads();
-  {
-    // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (region row 0 = image row R0 - 2, column 0 = C0 - 2)
-    h8 wa[9][2];
-    float bv[2][4];
-    load_mid_weights(wh + kW3, wq + kB3, wa, bv);
-    for (int task = wave; task < kG3 * 2; task += kFThreads / 64) {
-      const int grp = task >> 1, half = task & 1;
-      const int ro = grp * kRows;  // a3 region row (row 0 = image row R0 - 1)
-      fused_mid_tile(a2, kC2, ro, 16 * half, wa, bv, a3, kC3, ro, 16 * half, R0 - 1 + ro, C0 - 1 + 16 * half, H, W);
-    }
+  L4Consts k4;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) k4.wa[t] = ops->l4[t][l];
+  k4.b4 = wq[kB4];
+  // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (region row 0 = image row R0 - 2, column 0 = C0 - 2)
+  for (int task = wave; task < kG3 * 2; task += kFThreads / 64) {
+    const int grp = task >> 1, half = task & 1;
+    const int ro = grp * kRows;  // a3 region row (row 0 = image row R0 - 1)
+    fused_mid_tile(a2, kC2, ro, 16 * half, wa3, bv3, a3, kC3, ro, 16 * half, R0 - 1 + ro, C0 - 1 + 16 * half, H, W);
   }
   __syncthreads();
   {
     // layer 4 on the tile's pixels (a3 region row 0 = image row R0 - 1, column 0 = C0 - 1)
-    L4Consts k4;
-    l4_consts(wh, wq, k4);
     constexpr int kG4 = (kTH + kRows - 1) / kRows;
     for (int task = wave; task < kG4 * 2; task += kFThreads / 64) {
       const int grp = task >> 1, half = task & 1;
