@@ -200,17 +200,29 @@ __device__ __forceinline__ void l1_consts(const _Float16 *__restrict__ wh, const
   }
 }
 
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+// relu(z) for four FP32 sums as FP16, two to a word.  The conversion rounds to
+// nearest and keeps the sign, so taking the ReLU after it gives the same
+// values (a negative sum may leave -0, which counts as zero everywhere).
+__device__ __forceinline__ uint2 relu_pack(f4 z) {
+  const h2 zero = {static_cast<_Float16>(0.0f), static_cast<_Float16>(0.0f)};
+  const h2 lo = __builtin_elementwise_max(__builtin_convertvector(f2{z[0], z[1]}, h2), zero);
+  const h2 hi = __builtin_elementwise_max(__builtin_convertvector(f2{z[2], z[3]}, h2), zero);
+  return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+}
+
 // The lane's four channels 16m + 4g .. + 3 of a1 for its pixel, as two packed
 // words per half m, from the B operand bp (the pixel's taps 4g .. 4g + 3)
 __device__ __forceinline__ void l1_pixel(const L1Consts &c, h4 bp, uint2 (&out)[2]) {
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const f4 d = __builtin_amdgcn_mfma_f32_16x16x16f16(c.wa[m], bp, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    uint32_t hb[4];
+    f4 z;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      hb[r] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(d[r] * kInv255 + c.bv[m][r], 0.0f)));
-    out[m] = make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+    for (int r = 0; r < 4; ++r) z[r] = d[r] * kInv255 + c.bv[m][r];
+    out[m] = relu_pack(z);
   }
 }
 
@@ -338,9 +350,12 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
     const int b = static_cast<int>(gid / row_groups);
     const int r0 = static_cast<int>(gid - static_cast<uint32_t>(b) * row_groups) * kRows;
     const int c = static_cast<int>((tile - gid * col_tiles) * 16u) + i;
+    // forward: the bias is the addend of each sum's first product
     f4 acc[kRows][2];
 #pragma unroll
-    for (int j = 0; j < kRows; ++j) acc[j][0] = acc[j][1] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < kRows; ++j)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) acc[j][m] = f4{bv[m][0], bv[m][1], bv[m][2], bv[m][3]};
 #pragma unroll
     for (int k = 0; k < kRows + 2; ++k) {  // input row r0 - 1 + k
       // one input row's loads in flight at a time (the accumulators pass through
@@ -380,22 +395,21 @@ __global__ __launch_bounds__(kThreads) void mid_kernel(ImageSet s, const _Float1
         const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-          uint32_t hb[4];
+          uint2 w;
           if constexpr (kBwd) {
             const uint2 mw = *reinterpret_cast<const uint2 *>(mask + p * kC + 16 * m + 4 * g);
             const uint32_t mv[4] = {mw.x & 0xffffu, mw.x >> 16, mw.y & 0xffffu, mw.y >> 16};
+            uint32_t hb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const float a = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(mv[q])));
               hb[q] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(a > 0.0f ? acc[j][m][q] : 0.0f));
             }
+            w = make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
           } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              hb[q] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][q] + bv[m][q], 0.0f)));
+            w = relu_pack(acc[j][m]);
           }
-          *reinterpret_cast<uint2 *>(aout + p * kC + 16 * m + 4 * g) =
-              make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+          *reinterpret_cast<uint2 *>(aout + p * kC + 16 * m + 4 * g) = w;
         }
       }
     }
@@ -730,7 +744,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 // leave LDS and only the decoded and the output pixels touch HBM.  Positions
 // outside the image hold zeros at every layer (the network's zero padding).
 // Every layer runs on the matrix cores through the same functions as the
-// one-layer kernels of the training pass (l1_pixel, mid tiles, l4_tile), with
+// one-layer kernels of the training pass (l1_pixel, relu_pack, l4_tile), with
 // the same operands in the same order, so the output is the rounding of the y
 // those kernels form.
 //
@@ -738,22 +752,28 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 //   a3  rows -1 .. 3 kG3 - 2, columns -1 .. 30  (kG3 row groups x two 16-column halves)
 //   a2  rows -2 .. 3 kG2 - 3, columns -2 .. 31  (kG2 groups x two halves; columns 30, 31
 //       are read only by a3 columns past the tile and are never written)
-//   a1  rows -3 .. 3 kG1 - 4, columns -3 .. 30  (kG1 groups x three 16-column thirds, the
-//       last cut at column 30)
+//   a1  rows -3 .. 3 kG2 - 2, columns -3 .. 30  (its kR1 x kC1 pixels in runs of 16)
 //   P   rows -4 .., columns -4 .. 31 (the decoded pixels, FP16)
 //
 // Activations are stored pixel-major, 64 bytes per pixel, its four 16-byte
-// channel groups G permuted within the pixel to slot G ^ ((q >> 2) & 3) for the
-// pixel's index q in its region: the eight lanes that one 16-byte LDS access
-// serves read consecutive pixels, and their groups then fall in eight
-// different 16-byte bank ranges.
+// channel groups G permuted within the pixel to slot G ^ ((C >> 2) & 3) for the
+// pixel's column C in its region: the lanes that one 16-byte LDS access serves
+// read consecutive columns of one row, and their groups then fall in different
+// 16-byte bank ranges.  Since the permutation depends on the column only, a
+// lane's address for row R is its row-0 address plus R times the row pitch, a
+// constant offset of the LDS instruction.
+//
+// The tasks of the 32 -> 32 layers and of layer 4 are (row group, half) pairs
+// dealt to the waves in turn; with an even number of waves a wave always gets
+// the same half, so its lane addresses are fixed for the whole launch.
 inline constexpr int kTW = 28;                          // output columns of a tile
 inline constexpr int kTH = 26;                          // output rows of a tile
 inline constexpr int kFThreads = 512;                   // eight waves
+inline constexpr int kFWaves = kFThreads / 64;
+static_assert(kFWaves % 2 == 0, "a wave keeps its half");
 inline constexpr int kG3 = (kTH + 2 + kRows - 1) / kRows;      // a3 row groups
 inline constexpr int kG2 = (3 * kG3 + 2 + kRows - 1) / kRows;  // a2 row groups (cover a3's rows +- 1)
-inline constexpr int kG1 = (3 * kG2 + 2 + kRows - 1) / kRows;  // a1 row groups (cover a2's rows +- 1)
-inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = 3 * kG1, kRX = kR1 + 2;  // rows held
+inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = kR2 + 2, kRX = kR1 + 2;  // rows held
 inline constexpr int kC3 = 32, kC2 = 34, kC1 = 34, kCX = 36;                     // columns held
 inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; a3 later reuses this space
 inline constexpr int kLdsA2 = kR2 * kC2 * kC * 2;
@@ -761,27 +781,28 @@ inline constexpr int kLdsX = kRX * kCX * 2;
 static_assert(kR3 * kC3 * kC * 2 <= kLdsA1, "a3 fits in a1's space");
 static_assert(kLdsA1 + kLdsA2 + kLdsX <= 160 * 1024, "the tile fits in one CU's LDS");
 
-// byte offset of channel group G of pixel q (index in its region)
-__device__ __forceinline__ int act_slot(int q, int G) { return (q * 4 + (G ^ ((q >> 2) & 3))) * 16; }
+// byte offset of channel group G of the pixel with index q (row-major in its
+// region) and column C
+__device__ __forceinline__ int act_off(int q, int C, int G) { return q * 64 + 16 * (G ^ ((C >> 2) & 3)); }
 
-// 32 -> 32 layer on a 16-pixel x kRows tile, operands from LDS: `ain` holds a
-// region of cin columns whose column 0 is one to the left of this tile's column
-// 0 and whose row 0 is one above its row 0 (rin0 rows down); the tile writes
-// rows rout0 .. + kRows - 1, columns cout0 + i of `aout` (cout columns), zero where
-// the image position (img_r0 + j, img_c0 + i) lies outside the image.
-__device__ __forceinline__ void fused_mid_tile(const uint8_t *ain, int cin, int rin0, int cin0,
-                                               const h8 (&wa)[9][2], const float (&bv)[2][4], uint8_t *aout,
-                                               int cout, int rout0, int cout0, int img_r0, int img_c0, int H,
-                                               int W) {
-  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+// 32 -> 32 layer on a 16-pixel x kRows tile, operands from LDS.  `src` is the
+// input region's row one above the tile's row 0 (kCin columns); rd[dx] is the
+// lane's offset of its B operand at column offset dx in that row.  The tile
+// writes kRows rows from `dst` (the output region's row of the tile's row 0,
+// kCout columns) at the lane's offsets wr[m]; a row is zero unless row_in says it
+// lies in the image, and a lane's pixel is zero unless col_in.
+template <int kCin, int kCout>
+__device__ __forceinline__ void fused_mid_tile(const uint8_t *src, const int (&rd)[3], const h8 (&wa)[9][2],
+                                               const f4 (&bias)[2], uint8_t *dst, const int (&wr)[2],
+                                               bool col_in, const bool (&row_in)[kRows]) {
   f4 acc[kRows][2];
 #pragma unroll
-  for (int j = 0; j < kRows; ++j) acc[j][0] = acc[j][1] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < kRows; ++j) acc[j][0] = bias[0], acc[j][1] = bias[1];
 #pragma unroll
-  for (int k = 0; k < kRows + 2; ++k) {  // input row (rin0 + k), image row img_r0 - 1 + k
+  for (int k = 0; k < kRows + 2; ++k) {
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const h8 bx = *reinterpret_cast<const h8 *>(ain + act_slot((rin0 + k) * cin + cin0 + i + dx, g));
+      const h8 bx = *reinterpret_cast<const h8 *>(src + rd[dx] + k * (kCin * 64));
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         const int dy = k - j;
@@ -793,27 +814,21 @@ __device__ __forceinline__ void fused_mid_tile(const uint8_t *ain, int cin, int 
       }
     }
   }
-  const int c = img_c0 + i;
 #pragma unroll
   for (int j = 0; j < kRows; ++j) {
-    const int r = img_r0 + j;
-    const bool in = r >= 0 && r < H && c >= 0 && c < W;
-    const int q = (rout0 + j) * cout + cout0 + i;
+    const bool in = col_in && row_in[j];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      uint32_t hb[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        hb[t] = in ? __builtin_bit_cast(uint16_t, static_cast<_Float16>(fmaxf(acc[j][m][t] + bv[m][t], 0.0f))) : 0u;
-      *reinterpret_cast<uint2 *>(aout + act_slot(q, 2 * m + (g >> 1)) + 8 * (g & 1)) =
-          make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+      const uint2 w = relu_pack(acc[j][m]);
+      *reinterpret_cast<uint2 *>(dst + wr[m] + j * (kCout * 64)) = in ? w : make_uint2(0u, 0u);
     }
   }
 }
 
-// a mid layer's A operands (layer 0: W2, 1: W3) and biases for this lane
+// a mid layer's A operands (layer 0: W2, 1: W3) and biases for this lane, the
+// bias of output half m as the addend of its sums (D row 4g + r = channel 16m + 4g + r)
 __device__ __forceinline__ void load_mid_ops(const WeightOps *__restrict__ ops, int layer,
-                                             const float *__restrict__ bias, h8 (&wa)[9][2], float (&bv)[2][4]) {
+                                             const float *__restrict__ bias, h8 (&wa)[9][2], f4 (&bv)[2]) {
   const int l = threadIdx.x & 63, g = l >> 4;
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -841,6 +856,20 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l = tid & 63, i = l & 15, g = l >> 4;
+  const int half = wave & 1;
+  // the lane's offsets in a row of a region: B operands at columns 16 half + i + dx,
+  // results at column 16 half + i (every region is addressed from its column 0)
+  int rd[3], wr[2];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) {
+    const int C = 16 * half + i + dx;
+    rd[dx] = act_off(C, C, g);
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int C = 16 * half + i;
+    wr[m] = act_off(C, C, 2 * m + (g >> 1)) + 8 * (g & 1);
+  }
   L1Consts k1;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
@@ -849,7 +878,7 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
     for (int r = 0; r < 4; ++r) k1.bv[m][r] = wq[kB1 + 16 * m + 4 * g + r];
   }
   h8 wa2[9][2];
-  float bv2[2][4];
+  f4 bv2[2];
   load_mid_ops(ops, 0, wq + kB2, wa2, bv2);
   // the decoded pixels P on rows R0 - 4 .., columns C0 - 4 .., zero outside the image
   for (int k = tid; k < kRX * kCX; k += kFThreads) {
@@ -860,69 +889,82 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
   }
   __syncthreads();
   {
-    // layer 1: a1 rows -3 .., columns -3 .. 30 (region row 0 = image row R0 - 3,
-    // column 0 = C0 - 3; P region row 0 = image row R0 - 4)
-    for (int task = wave; task < kG1 * 3; task += kFThreads / 64) {
-      const int grp = task / 3, third = task - grp * 3;
-      const int col = 16 * third + i;
+    // layer 1 on the a1 region (row 0 = image row R0 - 3, column 0 = C0 - 3) in
+    // runs of 16 pixels; tap t = (t / 3, t % 3) of a1 pixel (R, C) is P region
+    // pixel (R + t / 3, C + t % 3).  Taps 9 .. 15 have zero weights, so their B
+    // entries may read any P value.
+    constexpr int kPx1 = kR1 * kC1, kRuns1 = (kPx1 + 15) / 16;
+    int toff[4];
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) {
-        const int rr = grp * kRows + j;
-        h4 bp;
+    for (int e = 0; e < 4; ++e) {
+      const int t = 4 * g + e;
+      toff[e] = t < 9 ? t / 3 * kCX + t % 3 : 0;
+    }
+    for (int u = wave; u < kRuns1; u += kFWaves) {
+      const int q = min(16 * u + i, kPx1 - 1);
+      const int R = static_cast<int>(static_cast<uint32_t>(q) / static_cast<uint32_t>(kC1)), C = q - R * kC1;
+      const _Float16 *px = xs + R * kCX + C;
+      h4 bp;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int t = 4 * g + e;
-          // tap (t / 3, t % 3) of a1 region (rr, col) is P region (rr + t / 3, col + t % 3)
-          bp[e] = t < 9 && col < kC1 ? xs[(rr + t / 3) * kCX + col + t % 3] : static_cast<_Float16>(0.0f);
-        }
-        uint2 o[2];
-        l1_pixel(k1, bp, o);
-        if (col < kC1) {
-          const int ir = R0 - 3 + rr, ic = C0 - 3 + col;
-          const bool in = ir >= 0 && ir < H && ic >= 0 && ic < W;
-          const int q = rr * kC1 + col;
+      for (int e = 0; e < 4; ++e) bp[e] = px[toff[e]];
+      uint2 o[2];
+      l1_pixel(k1, bp, o);
+      if (16 * u + i < kPx1) {
+        const int ir = R0 - 3 + R, ic = C0 - 3 + C;
+        const bool in = static_cast<uint32_t>(ir) < static_cast<uint32_t>(H) &&
+                        static_cast<uint32_t>(ic) < static_cast<uint32_t>(W);
 #pragma unroll
-          for (int m = 0; m < 2; ++m)
-            *reinterpret_cast<uint2 *>(a1 + act_slot(q, 2 * m + (g >> 1)) + 8 * (g & 1)) =
-                in ? o[m] : make_uint2(0u, 0u);
-        }
+        for (int m = 0; m < 2; ++m)
+          *reinterpret_cast<uint2 *>(a1 + act_off(q, C, 2 * m + (g >> 1)) + 8 * (g & 1)) =
+              in ? o[m] : make_uint2(0u, 0u);
       }
     }
   }
   __syncthreads();
   h8 wa3[9][2];
-  float bv3[2][4];
+  f4 bv3[2];
   load_mid_ops(ops, 1, wq + kB3, wa3, bv3);
-  // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (region row 0 = image row R0 - 3, column 0 = C0 - 3)
-  for (int task = wave; task < kG2 * 2; task += kFThreads / 64) {
-    const int grp = task >> 1, half = task & 1;
-    const int ro = grp * kRows;  // a2 region row (row 0 = image row R0 - 2)
-    fused_mid_tile(a1, kC1, ro, 16 * half, wa2, bv2, a2, kC2, ro, 16 * half, R0 - 2 + ro, C0 - 2 + 16 * half, H, W);
+  {
+    // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (a1 region row 0 = image row
+    // R0 - 3; a2 region row 0 = image row R0 - 2, column 0 = C0 - 2)
+    const bool col_in = static_cast<uint32_t>(C0 - 2 + 16 * half + i) < static_cast<uint32_t>(W);
+    for (int grp = wave >> 1; grp < kG2; grp += kFWaves / 2) {
+      const int ro = grp * kRows;
+      bool row_in[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 2 + ro + j) < static_cast<uint32_t>(H);
+      fused_mid_tile<kC1, kC2>(a1 + ro * (kC1 * 64), rd, wa2, bv2, a2 + ro * (kC2 * 64), wr, col_in, row_in);
+    }
   }
   __syncthreads();
   L4Consts k4;
 #pragma unroll
   for (int t = 0; t < 9; ++t) k4.wa[t] = ops->l4[t][l];
   k4.b4 = wq[kB4];
-  // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (region row 0 = image row R0 - 2, column 0 = C0 - 2)
-  for (int task = wave; task < kG3 * 2; task += kFThreads / 64) {
-    const int grp = task >> 1, half = task & 1;
-    const int ro = grp * kRows;  // a3 region row (row 0 = image row R0 - 1)
-    fused_mid_tile(a2, kC2, ro, 16 * half, wa3, bv3, a3, kC3, ro, 16 * half, R0 - 1 + ro, C0 - 1 + 16 * half, H, W);
+  {
+    // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (a3 region row 0 = image row
+    // R0 - 1, column 0 = C0 - 1)
+    const bool col_in = static_cast<uint32_t>(C0 - 1 + 16 * half + i) < static_cast<uint32_t>(W);
+    for (int grp = wave >> 1; grp < kG3; grp += kFWaves / 2) {
+      const int ro = grp * kRows;
+      bool row_in[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 1 + ro + j) < static_cast<uint32_t>(H);
+      fused_mid_tile<kC2, kC3>(a2 + ro * (kC2 * 64), rd, wa3, bv3, a3 + ro * (kC3 * 64), wr, col_in, row_in);
+    }
   }
   __syncthreads();
   {
     // layer 4 on the tile's pixels (a3 region row 0 = image row R0 - 1, column 0 = C0 - 1)
     constexpr int kG4 = (kTH + kRows - 1) / kRows;
-    for (int task = wave; task < kG4 * 2; task += kFThreads / 64) {
-      const int grp = task >> 1, half = task & 1;
-      const int r0 = grp * kRows, col = 16 * half + i;  // output tile coordinates
+    const int col = 16 * half + i, c = C0 + col;  // output tile column, image column
+    for (int grp = wave >> 1; grp < kG4; grp += kFWaves / 2) {
+      const int r0 = grp * kRows;
+      const uint8_t *src = a3 + r0 * (kC3 * 64);
       f4 acc[kRows];
-      l4_tile(k4.wa, [&](int k, int dx) {
-        // input row k is a3 region row r0 + k, column offset dx is a3 region column col + dx
-        return *reinterpret_cast<const h8 *>(a3 + act_slot((r0 + k) * kC3 + col + dx, g));
-      }, acc);
-      const int c = C0 + col;
+      // input row k is a3 region row r0 + k, column offset dx is a3 region column col + dx
+      l4_tile(k4.wa, [&](int k, int dx) { return *reinterpret_cast<const h8 *>(src + rd[dx] + k * (kC3 * 64)); },
+              acc);
       if (g == 0 && col < kTW && c < W) {
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
