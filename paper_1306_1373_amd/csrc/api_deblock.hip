@@ -240,14 +240,17 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
     fused_apply_kernel<<<tiles, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, wq, ops, out, out_stride);
     return launched();
   }
-  // every layer in tiles of kRows rows x 16 pixels of one image: ceil(h / kRows) x ceil(w / 16) per image
+  // layers 1 to 3 in tiles of kRows rows x 16 pixels of one image, ceil(h / kRows) x ceil(w / 16) per
+  // image; layer 4 in tiles of kRows rows x kL4Cols pixels
   const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   layer1_kernel<<<mgrid, kThreads, 0, s>>>(set, wq, wh, a1, ntiles);
   mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a1, wh + kW2, wq + kB2, nullptr, a2, npix, ntiles);
   mid_kernel<false><<<mgrid, kThreads, 0, s>>>(set, a2, wh + kW3, wq + kB3, nullptr, a3, npix, ntiles);
-  const unsigned lgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, kLossGroups));
-  layer4_kernel<<<lgrid, kThreads, 0, s>>>(set, a3, wq, wh, ntiles, y, g4, sq, 2.0f / static_cast<float>(npix),
+  const int64_t ntiles4 =
+      static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + kL4Cols - 1) / kL4Cols);
+  const unsigned lgrid = static_cast<unsigned>(std::min<int64_t>((ntiles4 + 3) / 4, kLossGroups));
+  layer4_kernel<<<lgrid, kThreads, 0, s>>>(set, a3, wq, wh, ntiles4, y, g4, sq, 2.0f / static_cast<float>(npix),
                                           signal_scale(npix));
   if (grad != nullptr) loss_reduce_kernel<<<1, kThreads, 0, s>>>(sq, static_cast<int>(lgrid), loss,
                                                                  1.0 / static_cast<double>(npix));

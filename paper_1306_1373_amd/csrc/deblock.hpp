@@ -38,10 +38,10 @@
 //                      and output channels swapped) and the taps mirrored, and
 //                      the ReLU mask of a_l in place of bias and ReLU
 //   layer4_kernel      a3 -> y (training), the loss terms and S dL/dy: the
-//                      32 -> 1 layer as the 32 -> 32 layers' GEMM with one
-//                      nonzero row of weights
+//                      32 -> 1 layer as one GEMM per input row with the nine
+//                      taps as its rows, then each pixel's nine tap sums added
 //   fused_apply_kernel inference in one launch: all four layers of a 28 x 26
-//                      output tile with x, a1, a2 and a3 held in LDS
+//                      output tile with x, a1, a2 and layer 4's tap sums in LDS
 //   bwd4_kernel        g3 from dL/dy through layer 4 and the ReLU of a3 (VALU,
 //                      one thread per pixel)
 //   wgrad_mid_kernel   weight and bias gradients of a 32 -> 32 layer as a GEMM
@@ -133,17 +133,18 @@ inline constexpr int kRows = 3;
 // whole set with 16-byte accesses, consecutive lanes at consecutive addresses
 // (prepared once per call from the FP16 weights):
 //   mid[layer][m][t][lane]  layers 2 and 3: W[16m + i][8g + e][t], e = 0..7
-//   l4[t][lane]             layer 4: W4[8g + e][t] in lane i = 0, zero elsewhere
+//   l4[lane]                layer 4: W4[4g + e][i] (e < 4), W4[12 + 4g + e][i] (e >= 4) for
+//                           taps i < 9, zero for i >= 9
 //   l1[m][lane]             layer 1: W1[16m + i][4g + e], e = 0..3 (taps 9.. zero)
 struct WeightOps {
   h8 mid[2][2][9][64];
-  h8 l4[9][64];
+  h8 l4[64];
   _Float16 l1[2][64][4];
 };
 
 __global__ __launch_bounds__(kThreads) void prep_ops_kernel(const _Float16 *__restrict__ wh, WeightOps *__restrict__ ops) {
   const int k = blockIdx.x * kThreads + threadIdx.x;  // one thread per 16-byte operand slot
-  constexpr int kMid = 2 * 2 * 9 * 64, kL4 = 9 * 64, kL1 = 2 * 64;
+  constexpr int kMid = 2 * 2 * 9 * 64, kL4 = 64, kL1 = 2 * 64;
   const _Float16 zero = static_cast<_Float16>(0.0f);
   if (k < kMid) {
     const int lane = k % 64, t = (k / 64) % 9, m = (k / (64 * 9)) % 2, layer = k / (64 * 9 * 2);
@@ -154,12 +155,12 @@ __global__ __launch_bounds__(kThreads) void prep_ops_kernel(const _Float16 *__re
     for (int e = 0; e < 8; ++e) v[e] = w[((16 * m + i) * kC + 8 * g + e) * 9 + t];
     ops->mid[layer][m][t][lane] = v;
   } else if (k < kMid + kL4) {
-    const int lane = (k - kMid) % 64, t = (k - kMid) / 64;
+    const int lane = k - kMid;
     const int i = lane & 15, g = lane >> 4;
     h8 v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = i == 0 ? wh[kW4 + (8 * g + e) * 9 + t] : zero;
-    ops->l4[t][lane] = v;
+    for (int e = 0; e < 8; ++e) v[e] = i < 9 ? wh[kW4 + (e < 4 ? 4 * g + e : 12 + 4 * g + e) * 9 + i] : zero;
+    ops->l4[lane] = v;
   } else if (k < kMid + kL4 + kL1) {
     const int lane = (k - kMid - kL4) % 64, m = (k - kMid - kL4) / 64;
     const int i = lane & 15, g = lane >> 4;
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void prep_ops_kernel(const _Float16 *__re
     }
   }
 }
-inline constexpr int kPrepOpsThreads = 2 * 2 * 9 * 64 + 9 * 64 + 2 * 64;
+inline constexpr int kPrepOpsThreads = 2 * 2 * 9 * 64 + 64 + 2 * 64;
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
@@ -226,48 +227,65 @@ __device__ __forceinline__ void l1_pixel(const L1Consts &c, h4 bp, uint2 (&out)[
   }
 }
 
-// Layer 4 on the matrix cores: the 32 -> 1 convolution as nine
-// v_mfma_f32_16x16x32_f16 per tile row with the tap's weights in M-row 0 of A
-// (the other rows zero) and the same B operands as the 32 -> 32 layers: lane
-// (i, 0) ends with sum_t sum_ci W4[ci][t] a3[pixel i + offset(t)][ci] in element
-// 0 of its accumulator.
+// Layer 4 on the matrix cores with the taps as the M dimension.  For 16
+// consecutive pixels p of an a3 row, one v_mfma_f32_16x16x32_f16 forms the
+// per-tap sums D[t][p] = sum_ci W4[ci][t] a3[p][ci] (A row t holds tap t's
+// weights, rows 9 .. 15 zero).  Its K index 8g + e stands for channel 4g + e
+// (e < 4) or 16 + 4g + e - 4 (e >= 4), so that a lane's B operand is exactly the
+// two packed words a 32 -> 32 layer leaves in lane (i, g) for pixel i (channels
+// 16m + 4g .. + 3 for m = 0, 1).  Output pixel (r, c) then adds its nine taps in
+// the order t = 3 dy + dx = 0 .. 8, D_t taken at a3 pixel (r + dy, c + dx):
+//   net = ((D_0 + D_1) + ...) + D_8,   y = p / 255 + (net + b4).
+// Every kernel that forms y uses l4_sums and l4_net, so the sums are the same
+// everywhere.
 struct L4Consts {
-  h8 wa[9];
+  h8 wa;  // A[i][8g + e] = W4[channel(g, e)][i] for taps i < 9
   float b4;
 };
+
+__device__ __forceinline__ int l4_channel(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + e - 4; }
 
 __device__ __forceinline__ void l4_consts(const _Float16 *__restrict__ wh, const float *__restrict__ wq,
                                           L4Consts &c) {
   const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      c.wa[t][e] = i == 0 ? wh[kW4 + (8 * g + e) * 9 + t] : static_cast<_Float16>(0.0f);
+  for (int e = 0; e < 8; ++e)
+    c.wa[e] = i < 9 ? wh[kW4 + l4_channel(g, e) * 9 + i] : static_cast<_Float16>(0.0f);
   c.b4 = wq[kB4];
 }
 
-// kRows tile rows of layer 4 (or of a 32 -> 32 layer's half m, with its weights
-// for wa): load(k, dx) gives the lane's B operand for input row k (0 ..
-// kRows + 1) and column offset dx; output row j uses input row k as tap row
-// k - j.  Shared by every kernel that forms these sums, so their order is the
-// same everywhere.
-template <class Load>
-__device__ __forceinline__ void l4_tile(const h8 (&wa)[9], Load load, f4 (&acc)[kRows]) {
-#pragma unroll
-  for (int j = 0; j < kRows; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int k = 0; k < kRows + 2; ++k)
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const h8 bx = load(k, dx);
-#pragma unroll
-      for (int j = 0; j < kRows; ++j) {
-        const int dy = k - j;
-        if (dy >= 0 && dy <= 2) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[dy * 3 + dx], bx, acc[j], 0, 0, 0);
-      }
-    }
+// the per-tap sums of the lane's pixel from its packed channels (w[m]: channels
+// 16m + 4g .. + 3): lane (i, g) gets taps 4g .. 4g + 3 of pixel i
+__device__ __forceinline__ f4 l4_sums(const h8 &wa, uint2 w0, uint2 w1) {
+  const h8 bx = __builtin_bit_cast(h8, make_uint4(w0.x, w0.y, w1.x, w1.y));
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(wa, bx, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 }
+
+// net of one output pixel from its nine per-tap sums, D(dy, dx, t)
+template <class Fetch>
+__device__ __forceinline__ float l4_net(Fetch D) {
+  float net = D(0, 0, 0);
+#pragma unroll
+  for (int t = 1; t < 9; ++t) net += D(t / 3, t % 3, t);
+  return net;
+}
+
+// every lane's LDS stores before any lane's loads (and loads before the next
+// stores) in a buffer private to the wave
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The training pass's layer-4 tiles: kRows output rows x kL4Cols columns, whose
+// sums come from kRows + 2 input rows of 16 columns, through a buffer per wave.
+// With these pitches the 48 lanes of a buffer store (lanes (i, g < 3), tap
+// 4g + r) and the 42 lanes of a gather (lanes (j, o)) each meet different banks.
+inline constexpr int kL4Cols = 14;
+inline constexpr int kL4TapPitch = 20;                        // floats per tap: 16 pixels + 4
+inline constexpr int kL4RowPitch = 12 * kL4TapPitch + 32;     // floats per input row (taps 0 .. 11)
+inline constexpr int kL4Buf = (kRows + 2) * kL4RowPitch;      // floats per wave
 
 // a1 = relu(conv(x; W1, b1)): a wave computes kRows rows x 16 columns of one image
 __global__ __launch_bounds__(kThreads) void layer1_kernel(ImageSet s, const float *__restrict__ wq,
@@ -424,55 +442,63 @@ __device__ __forceinline__ float residual(float p, float net) {
 }
 
 // Training forward of layer 4: y = x + conv(a3; W4, b4) on the matrix cores
-// (l4_tile, a wave per kRows rows x 16 columns of one image), then y to y_out
-// (if not null), the scaled signal S dL/dy = fp16(fp32(grad_scale (y - t)) S)
-// to g4, and the workgroup's sum of (y - t)^2 to sq[blockIdx.x] (summed in a
-// fixed order).
+// (l4_sums / l4_net, a wave per kRows rows x kL4Cols columns of one image), then
+// y to y_out (if not null), the scaled signal S dL/dy = fp16(fp32(grad_scale
+// (y - t)) S) to g4, and the workgroup's sum of (y - t)^2 to sq[blockIdx.x]
+// (summed in a fixed order).
 __global__ __launch_bounds__(kThreads) void layer4_kernel(ImageSet s, const _Float16 *__restrict__ a3,
                                                           const float *__restrict__ wq,
                                                           const _Float16 *__restrict__ wh, int64_t ntiles,
                                                           float *__restrict__ y_out, _Float16 *__restrict__ g4,
                                                           double *__restrict__ sq, float grad_scale, float S) {
+  __shared__ float bufs[kThreads / 64][kL4Buf];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  float *buf = bufs[wave];
   L4Consts k4;
   l4_consts(wh, wq, k4);
   double local = 0.0;
-  const uint32_t col_tiles = (static_cast<uint32_t>(s.w) + 15u) / 16u;
+  const uint32_t col_tiles = (static_cast<uint32_t>(s.w) + kL4Cols - 1u) / kL4Cols;
   const uint32_t row_groups = (static_cast<uint32_t>(s.h) + kRows - 1u) / kRows;
   const uint32_t step = gridDim.x * (kThreads / 64);
   for (uint32_t tile = blockIdx.x * (kThreads / 64) + wave; tile < static_cast<uint32_t>(ntiles); tile += step) {
     const uint32_t gid = tile / col_tiles;
     const int b = static_cast<int>(gid / row_groups);
     const int r0 = static_cast<int>(gid - static_cast<uint32_t>(b) * row_groups) * kRows;
-    const int c = static_cast<int>((tile - gid * col_tiles) * 16u) + i;
-    f4 acc[kRows];
-    l4_tile(k4.wa, [&](int k, int dx) {
-      const int rr = r0 - 1 + k, cc = c + dx - 1;
-      h8 bx;
-      if (rr >= 0 && rr < s.h && cc >= 0 && cc < s.w && c < s.w) {
-        bx = *reinterpret_cast<const h8 *>(a3 + ((static_cast<int64_t>(b) * s.h + rr) * s.w + cc) * kC + 8 * g);
-      } else {
+    const int c0 = static_cast<int>((tile - gid * col_tiles) * kL4Cols);
+    const int cc = c0 - 1 + i;  // this lane's input column
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bx[e] = static_cast<_Float16>(0.0f);
+    for (int k = 0; k < kRows + 2; ++k) {
+      const int rr = r0 - 1 + k;
+      uint2 w[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
+      if (rr >= 0 && rr < s.h && cc >= 0 && cc < s.w) {
+        const _Float16 *px = a3 + ((static_cast<int64_t>(b) * s.h + rr) * s.w + cc) * kC + 4 * g;
+        w[0] = *reinterpret_cast<const uint2 *>(px);
+        w[1] = *reinterpret_cast<const uint2 *>(px + 16);
       }
-      return bx;
-    }, acc);
-    if (g == 0 && c < s.w) {
+      const f4 d = l4_sums(k4.wa, w[0], w[1]);
+      if (g < 3) {
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) {
-        const int r = r0 + j;
-        if (r < s.h) {
-          const float y = residual(plane_px(s, s.plane, b, r, c), acc[j][0] + k4.b4);
-          const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
-          const float e = y - plane_px(s, s.orig, b, r, c) * kInv255;
-          if (y_out) y_out[p] = y;
-          const float gv = grad_scale * e;
-          g4[p] = static_cast<_Float16>(gv * S);
-          local += static_cast<double>(e) * e;
-        }
+        for (int r = 0; r < 4; ++r) buf[k * kL4RowPitch + (4 * g + r) * kL4TapPitch + i] = d[r];
       }
     }
+    wave_sync();
+    if (l < kRows * kL4Cols) {
+      const int j = l / kL4Cols, o = l - j * kL4Cols;
+      const int r = r0 + j, c = c0 + o;
+      const float *src = buf + j * kL4RowPitch + o;
+      const float net = l4_net([&](int dy, int dx, int t) { return src[dy * kL4RowPitch + t * kL4TapPitch + dx]; });
+      if (r < s.h && c < s.w) {
+        const float y = residual(plane_px(s, s.plane, b, r, c), net + k4.b4);
+        const int64_t p = (static_cast<int64_t>(b) * s.h + r) * s.w + c;
+        const float e = y - plane_px(s, s.orig, b, r, c) * kInv255;
+        if (y_out) y_out[p] = y;
+        const float gv = grad_scale * e;
+        g4[p] = static_cast<_Float16>(gv * S);
+        local += static_cast<double>(e) * e;
+      }
+    }
+    wave_sync();
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, 64);
@@ -740,16 +766,19 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 //
 // A workgroup of kFThreads threads computes an output tile of kTW x kTH pixels
 // of one image.  Each layer is computed on the region the next one reads (one
-// pixel more on every side), so the tile's decoded pixels, a1, a2 and a3 never
+// pixel more on every side), so the tile's decoded pixels and activations never
 // leave LDS and only the decoded and the output pixels touch HBM.  Positions
 // outside the image hold zeros at every layer (the network's zero padding).
-// Every layer runs on the matrix cores through the same functions as the
-// one-layer kernels of the training pass (l1_pixel, relu_pack, l4_tile), with
-// the same operands in the same order, so the output is the rounding of the y
-// those kernels form.
+// Layer 3's results never reach LDS: the lane that forms them turns them into
+// layer 4's per-tap sums at once (l4_sums), and the last phase adds each output
+// pixel's nine sums.  Every layer runs on the matrix cores through the same
+// functions as the one-layer kernels of the training pass (l1_pixel, relu_pack,
+// l4_sums, l4_net), with the same operands in the same order, so the output is
+// the rounding of the y those kernels form.
 //
 // Regions, in rows and columns relative to the tile's top-left output pixel:
-//   a3  rows -1 .. 3 kG3 - 2, columns -1 .. 30  (kG3 row groups x two 16-column halves)
+//   a3  rows -1 .. 3 kG3 - 2, columns -1 .. 30  (kG3 row groups x two 16-column halves;
+//       held only as layer 4's per-tap sums)
 //   a2  rows -2 .. 3 kG2 - 3, columns -2 .. 31  (kG2 groups x two halves; columns 30, 31
 //       are read only by a3 columns past the tile and are never written)
 //   a1  rows -3 .. 3 kG2 - 2, columns -3 .. 30  (its kR1 x kC1 pixels in runs of 16)
@@ -763,8 +792,8 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 // lane's address for row R is its row-0 address plus R times the row pitch, a
 // constant offset of the LDS instruction.
 //
-// The tasks of the 32 -> 32 layers and of layer 4 are (row group, half) pairs
-// dealt to the waves in turn; with an even number of waves a wave always gets
+// The tasks of the 32 -> 32 layers are (row group, half) pairs dealt to the
+// waves in turn; with an even number of waves a wave always gets
 // the same half, so its lane addresses are fixed for the whole launch.
 inline constexpr int kTW = 28;                          // output columns of a tile
 inline constexpr int kTH = 26;                          // output rows of a tile
@@ -774,11 +803,15 @@ static_assert(kFWaves % 2 == 0, "a wave keeps its half");
 inline constexpr int kG3 = (kTH + 2 + kRows - 1) / kRows;      // a3 row groups
 inline constexpr int kG2 = (3 * kG3 + 2 + kRows - 1) / kRows;  // a2 row groups (cover a3's rows +- 1)
 inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = kR2 + 2, kRX = kR1 + 2;  // rows held
-inline constexpr int kC3 = 32, kC2 = 34, kC1 = 34, kCX = 36;                     // columns held
-inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; a3 later reuses this space
+inline constexpr int kC2 = 34, kC1 = 34, kCX = 36;                                // columns held
+inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; the layer-4 sums later reuse this space
 inline constexpr int kLdsA2 = kR2 * kC2 * kC * 2;
 inline constexpr int kLdsX = kRX * kCX * 2;
-static_assert(kR3 * kC3 * kC * 2 <= kLdsA1, "a3 fits in a1's space");
+// layer 4's per-tap sums of the a3 region: taps 0 .. 11 of kR3 rows x 32 columns
+// (taps 9 .. 11 zero); the pitches put the 48 lanes of a store and 64
+// consecutive output pixels of a gather in different banks
+inline constexpr int kDTap = 36, kDRow = 12 * kDTap + 44;  // floats
+static_assert(kR3 * kDRow * 4 <= kLdsA1, "the layer-4 sums fit in a1's space");
 static_assert(kLdsA1 + kLdsA2 + kLdsX <= 160 * 1024, "the tile fits in one CU's LDS");
 
 // byte offset of channel group G of the pixel with index q (row-major in its
@@ -787,14 +820,13 @@ __device__ __forceinline__ int act_off(int q, int C, int G) { return q * 64 + 16
 
 // 32 -> 32 layer on a 16-pixel x kRows tile, operands from LDS.  `src` is the
 // input region's row one above the tile's row 0 (kCin columns); rd[dx] is the
-// lane's offset of its B operand at column offset dx in that row.  The tile
-// writes kRows rows from `dst` (the output region's row of the tile's row 0,
-// kCout columns) at the lane's offsets wr[m]; a row is zero unless row_in says it
-// lies in the image, and a lane's pixel is zero unless col_in.
-template <int kCin, int kCout>
+// lane's offset of its B operand at column offset dx in that row.  w[j][m] gets
+// the lane's packed channels 16m + 4g .. + 3 of its pixel in tile row j: zero
+// unless row_in[j] and col_in say the pixel lies in the image.
+template <int kCin>
 __device__ __forceinline__ void fused_mid_tile(const uint8_t *src, const int (&rd)[3], const h8 (&wa)[9][2],
-                                               const f4 (&bias)[2], uint8_t *dst, const int (&wr)[2],
-                                               bool col_in, const bool (&row_in)[kRows]) {
+                                               const f4 (&bias)[2], bool col_in, const bool (&row_in)[kRows],
+                                               uint2 (&w)[kRows][2]) {
   f4 acc[kRows][2];
 #pragma unroll
   for (int j = 0; j < kRows; ++j) acc[j][0] = bias[0], acc[j][1] = bias[1];
@@ -819,8 +851,8 @@ __device__ __forceinline__ void fused_mid_tile(const uint8_t *src, const int (&r
     const bool in = col_in && row_in[j];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const uint2 w = relu_pack(acc[j][m]);
-      *reinterpret_cast<uint2 *>(dst + wr[m] + j * (kCout * 64)) = in ? w : make_uint2(0u, 0u);
+      const uint2 v = relu_pack(acc[j][m]);
+      w[j][m] = in ? v : make_uint2(0u, 0u);
     }
   }
 }
@@ -848,7 +880,7 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
                                                                 uint8_t *__restrict__ out, int out_stride) {
   extern __shared__ __align__(16) uint8_t lds[];
   uint8_t *a1 = lds;
-  uint8_t *a3 = lds;  // a1 is dead once a2 is formed
+  float *dsum = reinterpret_cast<float *>(lds);  // layer 4's per-tap sums; a1 is dead once a2 is formed
   uint8_t *a2 = lds + kLdsA1;
   _Float16 *xs = reinterpret_cast<_Float16 *>(lds + kLdsA1 + kLdsA2);
   const int tiles_x = (W + kTW - 1) / kTW;
@@ -900,23 +932,33 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
       const int t = 4 * g + e;
       toff[e] = t < 9 ? t / 3 * kCX + t % 3 : 0;
     }
-    for (int u = wave; u < kRuns1; u += kFWaves) {
-      const int q = min(16 * u + i, kPx1 - 1);
-      const int R = static_cast<int>(static_cast<uint32_t>(q) / static_cast<uint32_t>(kC1)), C = q - R * kC1;
-      const _Float16 *px = xs + R * kCX + C;
-      h4 bp;
+    // two runs per pass (u and u + kFWaves), their loads issued together; a run
+    // past the region's end computes from clamped positions and stores nothing
+    for (int u0 = wave; u0 < kRuns1; u0 += 2 * kFWaves) {
+      int q[2], R[2], C[2];
+      h4 bp[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) bp[e] = px[toff[e]];
-      uint2 o[2];
-      l1_pixel(k1, bp, o);
-      if (16 * u + i < kPx1) {
-        const int ir = R0 - 3 + R, ic = C0 - 3 + C;
-        const bool in = static_cast<uint32_t>(ir) < static_cast<uint32_t>(H) &&
-                        static_cast<uint32_t>(ic) < static_cast<uint32_t>(W);
+      for (int h = 0; h < 2; ++h) {
+        q[h] = min(16 * (u0 + h * kFWaves) + i, kPx1 - 1);
+        R[h] = static_cast<int>(static_cast<uint32_t>(q[h]) / static_cast<uint32_t>(kC1));
+        C[h] = q[h] - R[h] * kC1;
+        const _Float16 *px = xs + R[h] * kCX + C[h];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-          *reinterpret_cast<uint2 *>(a1 + act_off(q, C, 2 * m + (g >> 1)) + 8 * (g & 1)) =
-              in ? o[m] : make_uint2(0u, 0u);
+        for (int e = 0; e < 4; ++e) bp[h][e] = px[toff[e]];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint2 o[2];
+        l1_pixel(k1, bp[h], o);
+        if (16 * (u0 + h * kFWaves) + i < kPx1) {
+          const int ir = R0 - 3 + R[h], ic = C0 - 3 + C[h];
+          const bool in = static_cast<uint32_t>(ir) < static_cast<uint32_t>(H) &&
+                          static_cast<uint32_t>(ic) < static_cast<uint32_t>(W);
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+            *reinterpret_cast<uint2 *>(a1 + act_off(q[h], C[h], 2 * m + (g >> 1)) + 8 * (g & 1)) =
+                in ? o[m] : make_uint2(0u, 0u);
+        }
       }
     }
   }
@@ -933,13 +975,18 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
       bool row_in[kRows];
 #pragma unroll
       for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 2 + ro + j) < static_cast<uint32_t>(H);
-      fused_mid_tile<kC1, kC2>(a1 + ro * (kC1 * 64), rd, wa2, bv2, a2 + ro * (kC2 * 64), wr, col_in, row_in);
+      uint2 w[kRows][2];
+      fused_mid_tile<kC1>(a1 + ro * (kC1 * 64), rd, wa2, bv2, col_in, row_in, w);
+      uint8_t *dst = a2 + ro * (kC2 * 64);
+#pragma unroll
+      for (int j = 0; j < kRows; ++j)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) *reinterpret_cast<uint2 *>(dst + wr[m] + j * (kC2 * 64)) = w[j][m];
     }
   }
   __syncthreads();
   L4Consts k4;
-#pragma unroll
-  for (int t = 0; t < 9; ++t) k4.wa[t] = ops->l4[t][l];
+  k4.wa = ops->l4[l];
   k4.b4 = wq[kB4];
   {
     // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (a3 region row 0 = image row
@@ -950,31 +997,34 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
       bool row_in[kRows];
 #pragma unroll
       for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 1 + ro + j) < static_cast<uint32_t>(H);
-      fused_mid_tile<kC2, kC3>(a2 + ro * (kC2 * 64), rd, wa3, bv3, a3 + ro * (kC3 * 64), wr, col_in, row_in);
+      uint2 w[kRows][2];
+      fused_mid_tile<kC2>(a2 + ro * (kC2 * 64), rd, wa3, bv3, col_in, row_in, w);
+      // layer 4's per-tap sums of these a3 pixels, taps 4g .. 4g + 3 in lane (i, g)
+      float *drow = dsum + ro * kDRow + 4 * g * kDTap + 16 * half + i;
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const f4 d = l4_sums(k4.wa, w[j][0], w[j][1]);
+        if (g < 3) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) drow[j * kDRow + r * kDTap] = d[r];
+        }
+      }
     }
   }
   __syncthreads();
   {
-    // layer 4 on the tile's pixels (a3 region row 0 = image row R0 - 1, column 0 = C0 - 1)
-    constexpr int kG4 = (kTH + kRows - 1) / kRows;
-    const int col = 16 * half + i, c = C0 + col;  // output tile column, image column
-    for (int grp = wave >> 1; grp < kG4; grp += kFWaves / 2) {
-      const int r0 = grp * kRows;
-      const uint8_t *src = a3 + r0 * (kC3 * 64);
-      f4 acc[kRows];
-      // input row k is a3 region row r0 + k, column offset dx is a3 region column col + dx
-      l4_tile(k4.wa, [&](int k, int dx) { return *reinterpret_cast<const h8 *>(src + rd[dx] + k * (kC3 * 64)); },
-              acc);
-      if (g == 0 && col < kTW && c < W) {
-#pragma unroll
-        for (int j = 0; j < kRows; ++j) {
-          const int r = R0 + r0 + j;
-          if (r0 + j < kTH && r < H) {
-            const float y = residual(static_cast<float>(xs[(r0 + j + 4) * kCX + col + 4]), acc[j][0] + k4.b4);
-            const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
-            out[static_cast<size_t>(r) * out_stride + c] = static_cast<uint8_t>(v);
-          }
-        }
+    // layer 4: each output pixel adds its nine per-tap sums (a3 region row 0 =
+    // image row R0 - 1, column 0 = C0 - 1, so output (r, c) takes tap (dy, dx) at
+    // a3 pixel (r + dy, c + dx))
+    for (int q = tid; q < kTW * kTH; q += kFThreads) {
+      const int r = q / kTW, c = q - r * kTW;
+      const float *src = dsum + r * kDRow + c;
+      const float net = l4_net([&](int dy, int dx, int t) { return src[dy * kDRow + t * kDTap + dx]; });
+      const int ir = R0 + r, ic = C0 + c;
+      if (ir < H && ic < W) {
+        const float y = residual(static_cast<float>(xs[(r + 4) * kCX + c + 4]), net + k4.b4);
+        const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
+        out[static_cast<size_t>(ir) * out_stride + ic] = static_cast<uint8_t>(v);
       }
     }
   }
