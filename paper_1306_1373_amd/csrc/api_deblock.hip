@@ -226,20 +226,26 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   auto *a2 = reinterpret_cast<_Float16 *>(ws + L.a2);
   auto *a3 = reinterpret_cast<_Float16 *>(ws + L.a3);
   auto *g4 = reinterpret_cast<_Float16 *>(ws + L.g4);
-  prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
   if (out != nullptr) {
-    // inference: one workgroup per 28 x 26 output tile, everything in LDS
+    // inference: the operands prepared once, then workgroups that each keep a
+    // 28 x 26 output tile in LDS, one per CU, looping over the tiles
     constexpr int lds = kLdsA1 + kLdsA2 + kLdsX;
     static const hipError_t attr =
         hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_apply_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (attr != hipSuccess) return DCT_ERR_DEVICE;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      return DCT_ERR_DEVICE;
     auto *ops = reinterpret_cast<WeightOps *>(ws + L.ops);
-    prep_ops_kernel<<<grid_for(kPrepOpsThreads), kThreads, 0, s>>>(wh, ops);
-    const unsigned tiles = static_cast<unsigned>(((set.w + kTW - 1) / kTW) * ((set.h + kTH - 1) / kTH));
-    fused_apply_kernel<<<tiles, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, wq, ops, out, out_stride);
+    prep_ops_kernel<<<grid_for(kPrepOpsThreads), kThreads, 0, s>>>(params, ops);
+    const int64_t tiles = static_cast<int64_t>((set.w + kTW - 1) / kTW) * ((set.h + kTH - 1) / kTH);
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, cus));
+    fused_apply_kernel<<<grid, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, ops, out, out_stride);
     return launched();
   }
+  prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);
   // layers 1 to 3 in tiles of kRows rows x 16 pixels of one image, ceil(h / kRows) x ceil(w / 16) per
   // image; layer 4 in tiles of kRows rows x kL4Cols pixels
   const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);

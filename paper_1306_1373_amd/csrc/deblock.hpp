@@ -129,37 +129,42 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(const float *__restrict_
 // pixel rows a wave's tile computes
 inline constexpr int kRows = 3;
 
-// The matrix-core A operands of every lane, laid out so that a lane loads its
-// whole set with 16-byte accesses, consecutive lanes at consecutive addresses
-// (prepared once per call from the FP16 weights):
+// The inference operands: the matrix-core A operands of every lane, laid out so
+// that a lane loads its whole set with 16-byte accesses, consecutive lanes at
+// consecutive addresses, and the biases, all from the FP16-rounded weights
+// (prepared once per call from the FP32 master copy):
 //   mid[layer][m][t][lane]  layers 2 and 3: W[16m + i][8g + e][t], e = 0..7
 //   l4[lane]                layer 4: W4[4g + e][i] (e < 4), W4[12 + 4g + e][i] (e >= 4) for
 //                           taps i < 9, zero for i >= 9
 //   l1[m][lane]             layer 1: W1[16m + i][4g + e], e = 0..3 (taps 9.. zero)
+//   bias[l]                 b1, b2, b3; b4 in b4
 struct WeightOps {
   h8 mid[2][2][9][64];
   h8 l4[64];
   _Float16 l1[2][64][4];
+  float bias[3][kC];
+  float b4;
 };
 
-__global__ __launch_bounds__(kThreads) void prep_ops_kernel(const _Float16 *__restrict__ wh, WeightOps *__restrict__ ops) {
-  const int k = blockIdx.x * kThreads + threadIdx.x;  // one thread per 16-byte operand slot
-  constexpr int kMid = 2 * 2 * 9 * 64, kL4 = 64, kL1 = 2 * 64;
+__global__ __launch_bounds__(kThreads) void prep_ops_kernel(const float *__restrict__ p, WeightOps *__restrict__ ops) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;  // one thread per operand slot
+  constexpr int kMid = 2 * 2 * 9 * 64, kL4 = 64, kL1 = 2 * 64, kBias = 3 * kC + 1;
   const _Float16 zero = static_cast<_Float16>(0.0f);
+  auto h = [&](int idx) { return static_cast<_Float16>(p[idx]); };
   if (k < kMid) {
     const int lane = k % 64, t = (k / 64) % 9, m = (k / (64 * 9)) % 2, layer = k / (64 * 9 * 2);
     const int i = lane & 15, g = lane >> 4;
-    const _Float16 *w = wh + (layer == 0 ? kW2 : kW3);
+    const int w = layer == 0 ? kW2 : kW3;
     h8 v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = w[((16 * m + i) * kC + 8 * g + e) * 9 + t];
+    for (int e = 0; e < 8; ++e) v[e] = h(w + ((16 * m + i) * kC + 8 * g + e) * 9 + t);
     ops->mid[layer][m][t][lane] = v;
   } else if (k < kMid + kL4) {
     const int lane = k - kMid;
     const int i = lane & 15, g = lane >> 4;
     h8 v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = i < 9 ? wh[kW4 + (e < 4 ? 4 * g + e : 12 + 4 * g + e) * 9 + i] : zero;
+    for (int e = 0; e < 8; ++e) v[e] = i < 9 ? h(kW4 + (e < 4 ? 4 * g + e : 12 + 4 * g + e) * 9 + i) : zero;
     ops->l4[lane] = v;
   } else if (k < kMid + kL4 + kL1) {
     const int lane = (k - kMid - kL4) % 64, m = (k - kMid - kL4) / 64;
@@ -167,11 +172,18 @@ __global__ __launch_bounds__(kThreads) void prep_ops_kernel(const _Float16 *__re
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int t = 4 * g + e;
-      ops->l1[m][lane][e] = t < 9 ? wh[kW1 + (16 * m + i) * 9 + t] : zero;
+      ops->l1[m][lane][e] = t < 9 ? h(kW1 + (16 * m + i) * 9 + t) : zero;
     }
+  } else if (k < kMid + kL4 + kL1 + kBias) {
+    const int j = k - kMid - kL4 - kL1;
+    const int base[3] = {kB1, kB2, kB3};
+    if (j < 3 * kC)
+      ops->bias[j / kC][j % kC] = static_cast<float>(h(base[j / kC] + j % kC));
+    else
+      ops->b4 = static_cast<float>(h(kB4));
   }
 }
-inline constexpr int kPrepOpsThreads = 2 * 2 * 9 * 64 + 64 + 2 * 64;
+inline constexpr int kPrepOpsThreads = 2 * 2 * 9 * 64 + 64 + 2 * 64 + 3 * kC + 1;
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
@@ -806,7 +818,7 @@ inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = kR2 + 2, kRX = kR1 + 2;
 inline constexpr int kC2 = 34, kC1 = 34, kCX = 36;                                // columns held
 inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; the layer-4 sums later reuse this space
 inline constexpr int kLdsA2 = kR2 * kC2 * kC * 2;
-inline constexpr int kLdsX = kRX * kCX * 2;
+inline constexpr int kLdsX = 2 * kRX * kCX * 2;            // two P tiles
 // layer 4's per-tap sums of the a3 region: taps 0 .. 11 of kR3 rows x 32 columns
 // (taps 9 .. 11 zero); the pitches put the 48 lanes of a store and 64
 // consecutive output pixels of a gather in different banks
@@ -859,8 +871,8 @@ __device__ __forceinline__ void fused_mid_tile(const uint8_t *src, const int (&r
 
 // a mid layer's A operands (layer 0: W2, 1: W3) and biases for this lane, the
 // bias of output half m as the addend of its sums (D row 4g + r = channel 16m + 4g + r)
-__device__ __forceinline__ void load_mid_ops(const WeightOps *__restrict__ ops, int layer,
-                                             const float *__restrict__ bias, h8 (&wa)[9][2], f4 (&bv)[2]) {
+__device__ __forceinline__ void load_mid_ops(const WeightOps *__restrict__ ops, int layer, h8 (&wa)[9][2],
+                                             f4 (&bv)[2]) {
   const int l = threadIdx.x & 63, g = l >> 4;
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -869,22 +881,44 @@ __device__ __forceinline__ void load_mid_ops(const WeightOps *__restrict__ ops, 
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bv[m][r] = bias[16 * m + 4 * g + r];
+    for (int r = 0; r < 4; ++r) bv[m][r] = ops->bias[layer + 1][16 * m + 4 * g + r];
 }
 
-// The deblocked output plane of one decoded plane (W x H, pitch stride), tile by
-// tile.  Each layer's weights are loaded while the layer before it computes.
+// the P tile (decoded pixels on rows R0 - 4 .., columns C0 - 4 .., zero outside the
+// image): this thread's entries tid + kFThreads e
+inline constexpr int kXs = kRX * kCX;                                   // entries of a P tile
+inline constexpr int kXsPer = (kXs + kFThreads - 1) / kFThreads;
+__device__ __forceinline__ void fetch_p(const uint8_t *__restrict__ plane, int W, int H, int stride, int R0,
+                                        int C0, uint32_t (&v)[kXsPer]) {
+#pragma unroll
+  for (int e = 0; e < kXsPer; ++e) {
+    const int k = static_cast<int>(threadIdx.x) + kFThreads * e;
+    const int rr = R0 - 4 + k / kCX, cc = C0 - 4 + k % kCX;
+    v[e] = k < kXs && rr >= 0 && rr < H && cc >= 0 && cc < W ? plane[static_cast<size_t>(rr) * stride + cc] : 0u;
+  }
+}
+__device__ __forceinline__ void store_p(_Float16 *xs, const uint32_t (&v)[kXsPer]) {
+#pragma unroll
+  for (int e = 0; e < kXsPer; ++e) {
+    const int k = static_cast<int>(threadIdx.x) + kFThreads * e;
+    if (k < kXs) xs[k] = static_cast<_Float16>(static_cast<float>(v[e]));
+  }
+}
+
+// The deblocked output plane of one decoded plane (W x H, pitch stride).  Each
+// workgroup takes tiles blockIdx.x, + gridDim.x, ...; the next tile's pixels
+// are fetched while this one's middle layers run, into the other of two P
+// buffers, and each layer's weights are loaded while the layer before it
+// computes.
 __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *__restrict__ plane, int W, int H,
-                                                                int stride, const float *__restrict__ wq,
-                                                                const WeightOps *__restrict__ ops,
+                                                                int stride, const WeightOps *__restrict__ ops,
                                                                 uint8_t *__restrict__ out, int out_stride) {
   extern __shared__ __align__(16) uint8_t lds[];
   uint8_t *a1 = lds;
   float *dsum = reinterpret_cast<float *>(lds);  // layer 4's per-tap sums; a1 is dead once a2 is formed
   uint8_t *a2 = lds + kLdsA1;
-  _Float16 *xs = reinterpret_cast<_Float16 *>(lds + kLdsA1 + kLdsA2);
-  const int tiles_x = (W + kTW - 1) / kTW;
-  const int R0 = static_cast<int>(blockIdx.x) / tiles_x * kTH, C0 = static_cast<int>(blockIdx.x) % tiles_x * kTW;
+  _Float16 *xbuf = reinterpret_cast<_Float16 *>(lds + kLdsA1 + kLdsA2);  // two P tiles
+  const int tiles_x = (W + kTW - 1) / kTW, ntiles = tiles_x * ((H + kTH - 1) / kTH);
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l = tid & 63, i = l & 15, g = l >> 4;
@@ -907,112 +941,119 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
   for (int m = 0; m < 2; ++m) {
     k1.wa[m] = *reinterpret_cast<const h4 *>(ops->l1[m][l]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) k1.bv[m][r] = wq[kB1 + 16 * m + 4 * g + r];
+    for (int r = 0; r < 4; ++r) k1.bv[m][r] = ops->bias[0][16 * m + 4 * g + r];
   }
-  h8 wa2[9][2];
-  f4 bv2[2];
-  load_mid_ops(ops, 0, wq + kB2, wa2, bv2);
-  // the decoded pixels P on rows R0 - 4 .., columns C0 - 4 .., zero outside the image
-  for (int k = tid; k < kRX * kCX; k += kFThreads) {
-    const int rr = R0 - 4 + k / kCX, cc = C0 - 4 + k % kCX;
-    xs[k] = static_cast<_Float16>(rr >= 0 && rr < H && cc >= 0 && cc < W
-                                      ? static_cast<float>(plane[static_cast<size_t>(rr) * stride + cc])
-                                      : 0.0f);
+  // layer 1's tap offsets in the P tile for taps 4g + e (taps 9 .. 15 have zero
+  // weights, so their B entries may read any P value)
+  int toff[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int t = 4 * g + e;
+    toff[e] = t < 9 ? t / 3 * kCX + t % 3 : 0;
+  }
+  int tile = static_cast<int>(blockIdx.x);
+  if (tile >= ntiles) return;
+  {
+    uint32_t v[kXsPer];
+    fetch_p(plane, W, H, stride, tile / tiles_x * kTH, tile % tiles_x * kTW, v);
+    store_p(xbuf, v);
   }
   __syncthreads();
-  {
-    // layer 1 on the a1 region (row 0 = image row R0 - 3, column 0 = C0 - 3) in
-    // runs of 16 pixels; tap t = (t / 3, t % 3) of a1 pixel (R, C) is P region
-    // pixel (R + t / 3, C + t % 3).  Taps 9 .. 15 have zero weights, so their B
-    // entries may read any P value.
-    constexpr int kPx1 = kR1 * kC1, kRuns1 = (kPx1 + 15) / 16;
-    int toff[4];
+  for (int cur = 0; tile < ntiles; tile += static_cast<int>(gridDim.x), cur ^= 1) {
+    const int R0 = tile / tiles_x * kTH, C0 = tile % tiles_x * kTW;
+    const _Float16 *xs = xbuf + cur * kXs;
+    h8 wa2[9][2];
+    f4 bv2[2];
+    load_mid_ops(ops, 0, wa2, bv2);
+    {
+      // layer 1 on the a1 region (row 0 = image row R0 - 3, column 0 = C0 - 3) in
+      // runs of 16 pixels; tap t = (t / 3, t % 3) of a1 pixel (R, C) is P region
+      // pixel (R + t / 3, C + t % 3).  Two runs per pass (u and u + kFWaves), their
+      // loads issued together; a run past the region's end computes from clamped
+      // positions and stores nothing.
+      constexpr int kPx1 = kR1 * kC1, kRuns1 = (kPx1 + 15) / 16;
+      for (int u0 = wave; u0 < kRuns1; u0 += 2 * kFWaves) {
+        int q[2], R[2], C[2];
+        h4 bp[2];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int t = 4 * g + e;
-      toff[e] = t < 9 ? t / 3 * kCX + t % 3 : 0;
-    }
-    // two runs per pass (u and u + kFWaves), their loads issued together; a run
-    // past the region's end computes from clamped positions and stores nothing
-    for (int u0 = wave; u0 < kRuns1; u0 += 2 * kFWaves) {
-      int q[2], R[2], C[2];
-      h4 bp[2];
+        for (int h = 0; h < 2; ++h) {
+          q[h] = min(16 * (u0 + h * kFWaves) + i, kPx1 - 1);
+          R[h] = static_cast<int>(static_cast<uint32_t>(q[h]) / static_cast<uint32_t>(kC1));
+          C[h] = q[h] - R[h] * kC1;
+          const _Float16 *px = xs + R[h] * kCX + C[h];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        q[h] = min(16 * (u0 + h * kFWaves) + i, kPx1 - 1);
-        R[h] = static_cast<int>(static_cast<uint32_t>(q[h]) / static_cast<uint32_t>(kC1));
-        C[h] = q[h] - R[h] * kC1;
-        const _Float16 *px = xs + R[h] * kCX + C[h];
+          for (int e = 0; e < 4; ++e) bp[h][e] = px[toff[e]];
+        }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) bp[h][e] = px[toff[e]];
-      }
+        for (int h = 0; h < 2; ++h) {
+          uint2 o[2];
+          l1_pixel(k1, bp[h], o);
+          if (16 * (u0 + h * kFWaves) + i < kPx1) {
+            const int ir = R0 - 3 + R[h], ic = C0 - 3 + C[h];
+            const bool in = static_cast<uint32_t>(ir) < static_cast<uint32_t>(H) &&
+                            static_cast<uint32_t>(ic) < static_cast<uint32_t>(W);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint2 o[2];
-        l1_pixel(k1, bp[h], o);
-        if (16 * (u0 + h * kFWaves) + i < kPx1) {
-          const int ir = R0 - 3 + R[h], ic = C0 - 3 + C[h];
-          const bool in = static_cast<uint32_t>(ir) < static_cast<uint32_t>(H) &&
-                          static_cast<uint32_t>(ic) < static_cast<uint32_t>(W);
-#pragma unroll
-          for (int m = 0; m < 2; ++m)
-            *reinterpret_cast<uint2 *>(a1 + act_off(q[h], C[h], 2 * m + (g >> 1)) + 8 * (g & 1)) =
-                in ? o[m] : make_uint2(0u, 0u);
+            for (int m = 0; m < 2; ++m)
+              *reinterpret_cast<uint2 *>(a1 + act_off(q[h], C[h], 2 * m + (g >> 1)) + 8 * (g & 1)) =
+                  in ? o[m] : make_uint2(0u, 0u);
+          }
         }
       }
     }
-  }
-  __syncthreads();
-  h8 wa3[9][2];
-  f4 bv3[2];
-  load_mid_ops(ops, 1, wq + kB3, wa3, bv3);
-  {
-    // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (a1 region row 0 = image row
-    // R0 - 3; a2 region row 0 = image row R0 - 2, column 0 = C0 - 2)
-    const bool col_in = static_cast<uint32_t>(C0 - 2 + 16 * half + i) < static_cast<uint32_t>(W);
-    for (int grp = wave >> 1; grp < kG2; grp += kFWaves / 2) {
-      const int ro = grp * kRows;
-      bool row_in[kRows];
+    __syncthreads();
+    // the next tile's pixels, in flight through layers 2 and 3
+    const int next = tile + static_cast<int>(gridDim.x);
+    uint32_t pv[kXsPer];
+    if (next < ntiles) fetch_p(plane, W, H, stride, next / tiles_x * kTH, next % tiles_x * kTW, pv);
+    h8 wa3[9][2];
+    f4 bv3[2];
+    load_mid_ops(ops, 1, wa3, bv3);
+    {
+      // layer 2: a2 rows -2 .., columns -2 .. 29 from a1 (a1 region row 0 = image row
+      // R0 - 3; a2 region row 0 = image row R0 - 2, column 0 = C0 - 2)
+      const bool col_in = static_cast<uint32_t>(C0 - 2 + 16 * half + i) < static_cast<uint32_t>(W);
+      for (int grp = wave >> 1; grp < kG2; grp += kFWaves / 2) {
+        const int ro = grp * kRows;
+        bool row_in[kRows];
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 2 + ro + j) < static_cast<uint32_t>(H);
-      uint2 w[kRows][2];
-      fused_mid_tile<kC1>(a1 + ro * (kC1 * 64), rd, wa2, bv2, col_in, row_in, w);
-      uint8_t *dst = a2 + ro * (kC2 * 64);
+        for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 2 + ro + j) < static_cast<uint32_t>(H);
+        uint2 w[kRows][2];
+        fused_mid_tile<kC1>(a1 + ro * (kC1 * 64), rd, wa2, bv2, col_in, row_in, w);
+        uint8_t *dst = a2 + ro * (kC2 * 64);
 #pragma unroll
-      for (int j = 0; j < kRows; ++j)
+        for (int j = 0; j < kRows; ++j)
 #pragma unroll
-        for (int m = 0; m < 2; ++m) *reinterpret_cast<uint2 *>(dst + wr[m] + j * (kC2 * 64)) = w[j][m];
+          for (int m = 0; m < 2; ++m) *reinterpret_cast<uint2 *>(dst + wr[m] + j * (kC2 * 64)) = w[j][m];
+      }
     }
-  }
-  __syncthreads();
-  L4Consts k4;
-  k4.wa = ops->l4[l];
-  k4.b4 = wq[kB4];
-  {
-    // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (a3 region row 0 = image row
-    // R0 - 1, column 0 = C0 - 1)
-    const bool col_in = static_cast<uint32_t>(C0 - 1 + 16 * half + i) < static_cast<uint32_t>(W);
-    for (int grp = wave >> 1; grp < kG3; grp += kFWaves / 2) {
-      const int ro = grp * kRows;
-      bool row_in[kRows];
+    __syncthreads();
+    const h8 wa4 = ops->l4[l];
+    const float b4 = ops->b4;
+    {
+      // layer 3: a3 rows -1 .., columns -1 .. 30 from a2 (a3 region row 0 = image row
+      // R0 - 1, column 0 = C0 - 1)
+      const bool col_in = static_cast<uint32_t>(C0 - 1 + 16 * half + i) < static_cast<uint32_t>(W);
+      for (int grp = wave >> 1; grp < kG3; grp += kFWaves / 2) {
+        const int ro = grp * kRows;
+        bool row_in[kRows];
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 1 + ro + j) < static_cast<uint32_t>(H);
-      uint2 w[kRows][2];
-      fused_mid_tile<kC2>(a2 + ro * (kC2 * 64), rd, wa3, bv3, col_in, row_in, w);
-      // layer 4's per-tap sums of these a3 pixels, taps 4g .. 4g + 3 in lane (i, g)
-      float *drow = dsum + ro * kDRow + 4 * g * kDTap + 16 * half + i;
+        for (int j = 0; j < kRows; ++j) row_in[j] = static_cast<uint32_t>(R0 - 1 + ro + j) < static_cast<uint32_t>(H);
+        uint2 w[kRows][2];
+        fused_mid_tile<kC2>(a2 + ro * (kC2 * 64), rd, wa3, bv3, col_in, row_in, w);
+        // layer 4's per-tap sums of these a3 pixels, taps 4g .. 4g + 3 in lane (i, g)
+        float *drow = dsum + ro * kDRow + 4 * g * kDTap + 16 * half + i;
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) {
-        const f4 d = l4_sums(k4.wa, w[j][0], w[j][1]);
-        if (g < 3) {
+        for (int j = 0; j < kRows; ++j) {
+          const f4 d = l4_sums(wa4, w[j][0], w[j][1]);
+          if (g < 3) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) drow[j * kDRow + r * kDTap] = d[r];
+            for (int r = 0; r < 4; ++r) drow[j * kDRow + r * kDTap] = d[r];
+          }
         }
       }
     }
-  }
-  __syncthreads();
-  {
+    if (next < ntiles) store_p(xbuf + (cur ^ 1) * kXs, pv);
+    __syncthreads();
     // layer 4: each output pixel adds its nine per-tap sums (a3 region row 0 =
     // image row R0 - 1, column 0 = C0 - 1, so output (r, c) takes tap (dy, dx) at
     // a3 pixel (r + dy, c + dx))
@@ -1022,11 +1063,12 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
       const float net = l4_net([&](int dy, int dx, int t) { return src[dy * kDRow + t * kDTap + dx]; });
       const int ir = R0 + r, ic = C0 + c;
       if (ir < H && ic < W) {
-        const float y = residual(static_cast<float>(xs[(r + 4) * kCX + c + 4]), net + k4.b4);
+        const float y = residual(static_cast<float>(xs[(r + 4) * kCX + c + 4]), net + b4);
         const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
         out[static_cast<size_t>(ir) * out_stride + ic] = static_cast<uint8_t>(v);
       }
     }
+    __syncthreads();
   }
 }
 
