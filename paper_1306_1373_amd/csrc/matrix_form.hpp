@@ -349,6 +349,18 @@ __device__ __forceinline__ void store_words(uint8_t *__restrict__ dst, int W, in
   }
 }
 
+// SSE of the lane's four words of a block inside the image
+__device__ __forceinline__ uint32_t words_sse_full(const uint32_t (&a)[4], const uint32_t (&b)[4]) {
+  uint32_t pp = 0, pr = 0, rr = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    pp = __builtin_amdgcn_udot4(a[t], a[t], pp, false);
+    pr = __builtin_amdgcn_udot4(a[t], b[t], pr, false);
+    rr = __builtin_amdgcn_udot4(b[t], b[t], rr, false);
+  }
+  return pp - 2u * pr + rr;
+}
+
 // SSE of the lane's four words; edge blocks count only pixels inside W x H
 __device__ __forceinline__ uint32_t words_sse(const uint32_t (&a)[4], const uint32_t (&b)[4], int W, int H, int by,
                                               int bx, int g, bool full) {
@@ -538,27 +550,33 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
   // each wave walks its tiles with the words of the next kKronDepth tiles in flight
   const int step = gridDim.x * kMfmaWaves;
   int tile = blockIdx.x * kMfmaWaves + wave;
+  // (the position of each tile's blocks is found once, when its words are loaded)
   uint32_t ring[kKronDepth][4];
+  BlockPos rpos[kKronDepth];
 #pragma unroll
   for (int d = 0; d < kKronDepth; ++d) {
-    const BlockPos pd = tile_pos(tile + d * step, i, W, H, bw, nblocks);
+    rpos[d] = tile_pos(tile + d * step, i, W, H, bw, nblocks);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ring[d][k] = 0u;
-    if (tile + d * step < ntiles && pd.live) load_words(src, W, H, stride, pd.by, pd.bx, g, pd.full, ring[d]);
+    if (tile + d * step < ntiles && rpos[d].live)
+      load_words(src, W, H, stride, rpos[d].by, rpos[d].bx, g, rpos[d].full, ring[d]);
   }
   for (; tile < ntiles; tile += step) {
     const int b = tile * 16 + i;
-    const BlockPos p = tile_pos(tile, i, W, H, bw, nblocks);
+    const BlockPos p = rpos[0];
     uint32_t w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = ring[0][k];
 #pragma unroll
-    for (int d = 0; d + 1 < kKronDepth; ++d)
+    for (int d = 0; d + 1 < kKronDepth; ++d) {
+      rpos[d] = rpos[d + 1];
 #pragma unroll
       for (int k = 0; k < 4; ++k) ring[d][k] = ring[d + 1][k];
+    }
     {
       const int tn = tile + kKronDepth * step;
-      const BlockPos pn = tile_pos(tn, i, W, H, bw, nblocks);
+      BlockPos &pn = rpos[kKronDepth - 1];
+      pn = tile_pos(tn, i, W, H, bw, nblocks);
 #pragma unroll
       for (int k = 0; k < 4; ++k) ring[kKronDepth - 1][k] = 0u;
       if (tn < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, ring[kKronDepth - 1]);
@@ -575,9 +593,12 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
     } else {
       uint32_t rec[4];
       kron_code<kBf16>(kc, &inv, l, acc, rec);
-      if (p.live) {
-        store_words(dst, W, H, dst_stride, p.by, p.bx, g, p.full, rec);
-        err += words_sse(w, rec, W, H, p.by, p.bx, g, p.full);
+      if (p.full) {
+        store_words(dst, W, H, dst_stride, p.by, p.bx, g, true, rec);
+        err += words_sse_full(w, rec);
+      } else if (p.live) {
+        store_words(dst, W, H, dst_stride, p.by, p.bx, g, false, rec);
+        err += words_sse(w, rec, W, H, p.by, p.bx, g, false);
       }
     }
   }
