@@ -383,28 +383,27 @@ __device__ __forceinline__ uint32_t words_sse(const uint32_t (&a)[4], const uint
   return pp - 2u * pr + rr;
 }
 
-// Per-lane constants of the matrix form: the A operands of the forward product
-// and the quantizer entries of the 16 coefficients the lane holds.  The A
-// operands of the inverse product live in LDS (InverseTable), which keeps the
-// kernel within four waves per SIMD.
+// Per-lane constants of the matrix form: the quantizer entries of the 16
+// coefficients the lane holds.  The A operands of both products live in LDS
+// (OperandTable), which keeps the kernel within five waves per SIMD.
 template <bool kBf16>
 struct KronConsts {
-  typename MfmaTraits<kBf16>::vec fa[4][2];  // fa[t][s] = K[16t + i][sigma(s, g, e)]
-  float qv[4][4], rq[4][4];                  // Q and 1/Q of coefficient 16t + 4g + r
+  float qv[4][4], rq[4][4];  // Q and 1/Q of coefficient 16t + 4g + r
 };
 
-// The inverse product's A operands of every lane, ia[t][s][lane][e] =
-// K[sigma(s, g, e)][16t + i]: one 16-byte read per operand, consecutive lanes
-// at consecutive addresses.
+// The A operands of every lane: forward fa[t][s][lane][e] = K[16t + i][sigma(s,
+// g, e)], inverse ia[t][s][lane][e] = K[sigma(s, g, e)][16t + i]; one 16-byte
+// read per operand, consecutive lanes at consecutive addresses.
 template <bool kBf16>
-struct InverseTable {
+struct OperandTable {
+  typename MfmaTraits<kBf16>::vec fa[4][2][64];
   typename MfmaTraits<kBf16>::vec ia[4][2][64];
 };
 
-// Fills the lane's forward operands and quantizer entries, and (kCodec, wave 0)
-// the workgroup's inverse table; the caller synchronizes the workgroup after.
+// Fills the lane's quantizer entries and (wave 0) the workgroup's operand table
+// (the inverse half only when kCodec); the caller synchronizes the workgroup after.
 template <bool kBf16, bool kCodec>
-__device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, InverseTable<kBf16> *inv, const FloatQuant &fq,
+__device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, OperandTable<kBf16> *inv, const FloatQuant &fq,
                                            int wave, int i, int g) {
   using T = MfmaTraits<kBf16>;
   typedef typename T::elem elem;
@@ -414,14 +413,15 @@ __device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, InverseTable<k
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      typename T::vec ia;
+      typename T::vec fa, ia;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        kc.fa[t][s][e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
+        fa[e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
         if constexpr (kCodec) ia[e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
       }
-      if constexpr (kCodec) {
-        if (wave == 0) inv->ia[t][s][lane] = ia;
+      if (wave == 0) {
+        inv->fa[t][s][lane] = fa;
+        if constexpr (kCodec) inv->ia[t][s][lane] = ia;
       }
     }
   if constexpr (kCodec) {
@@ -445,7 +445,10 @@ __device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, InverseTable<k
 
 // forward product of the lane's 16 pixels (four words): acc[t][r] = coefficient 16t + 4g + r
 template <bool kBf16>
-__device__ __forceinline__ void kron_forward(const KronConsts<kBf16> &kc, const uint32_t (&w)[4], f32x4 (&acc)[4]) {
+__device__ __forceinline__ void kron_forward(const OperandTable<kBf16> *tab, int lane, const uint32_t (&w)[4],
+                                             f32x4 (&acc)[4]) {
+  // the table is read afresh at every call (an opaque index keeps the reads in the loop)
+  asm volatile("" : "+v"(lane));
   using T = MfmaTraits<kBf16>;
   typedef typename T::vec vec;
   typedef typename T::elem elem;
@@ -476,14 +479,14 @@ __device__ __forceinline__ void kron_forward(const KronConsts<kBf16> &kc, const 
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    acc[t] = T::mma(kc.fa[t][0], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
-    acc[t] = T::mma(kc.fa[t][1], bx[1], acc[t]);
+    acc[t] = T::mma(tab->fa[t][0][lane], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
+    acc[t] = T::mma(tab->fa[t][1][lane], bx[1], acc[t]);
   }
 }
 
 // quantize, dequantize, inverse product and reconstruction: the four output words
 template <bool kBf16>
-__device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const InverseTable<kBf16> *inv, int lane,
+__device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const OperandTable<kBf16> *inv, int lane,
                                           const f32x4 (&acc)[4], uint32_t (&rec)[4]) {
   // the table is read afresh at every call: an opaque index keeps the compiler
   // from hoisting the reads out of the tile loop into registers
@@ -542,10 +545,10 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
                                                               uint8_t *__restrict__ dst, int dst_stride,
                                                               unsigned long long *__restrict__ sse) {
   const int wave = wave_index(), l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-  __shared__ InverseTable<kBf16> inv;
+  __shared__ OperandTable<kBf16> inv;
   KronConsts<kBf16> kc;
   kron_setup<kBf16, kCodec>(kc, &inv, fq, wave, i, g);
-  if constexpr (kCodec) __syncthreads();
+  __syncthreads();
   uint64_t err = 0;
   // each wave walks its tiles with the words of the next kKronDepth tiles in flight
   const int step = gridDim.x * kMfmaWaves;
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
       if (tn < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, ring[kKronDepth - 1]);
     }
     f32x4 acc[4];
-    kron_forward<kBf16>(kc, w, acc);
+    kron_forward<kBf16>(&inv, l, w, acc);
     if constexpr (!kCodec) {
       if (p.live) {
 #pragma unroll
@@ -680,7 +683,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
                                                                   uint8_t *__restrict__ out_cr, int plane_stride,
                                                                   unsigned long long *__restrict__ sse) {
   const int wave = wave_index(), l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-  __shared__ InverseTable<kBf16> inv;
+  __shared__ OperandTable<kBf16> inv;
   KronConsts<kBf16> kc;
   kron_setup<kBf16, true>(kc, &inv, fq, wave, i, g);
   __syncthreads();
@@ -693,7 +696,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       f32x4 acc[4];
-      kron_forward<kBf16>(kc, w[c], acc);
+      kron_forward<kBf16>(&inv, l, w[c], acc);
       uint32_t rec[4];
       kron_code<kBf16>(kc, &inv, l, acc, rec);
       if (p.live) {
