@@ -383,32 +383,29 @@ __device__ __forceinline__ uint32_t words_sse(const uint32_t (&a)[4], const uint
   return pp - 2u * pr + rr;
 }
 
-// Per-lane constants of the matrix form: the quantizer entries of the 16
-// coefficients the lane holds.  The A operands of both products live in LDS
-// (OperandTable), which keeps the kernel within five waves per SIMD.
-template <bool kBf16>
-struct KronConsts {
-  float qv[4][4], rq[4][4];  // Q and 1/Q of coefficient 16t + 4g + r
-};
-
-// The A operands of every lane: forward fa[t][s][lane][e] = K[16t + i][sigma(s,
-// g, e)], inverse ia[t][s][lane][e] = K[sigma(s, g, e)][16t + i]; one 16-byte
-// read per operand, consecutive lanes at consecutive addresses.
+// The workgroup's constants of the matrix form, in LDS: the A operands of every
+// lane, forward fa[t][s][lane][e] = K[16t + i][sigma(s, g, e)] and inverse
+// ia[t][s][lane][e] = K[sigma(s, g, e)][16t + i] (one 16-byte read per operand,
+// consecutive lanes at consecutive addresses), and the quantizer entries of the
+// coefficients 16t + 4g + r that lane group g holds, qv[t][g][r] = Q and
+// rq[t][g][r] = 1/Q (one 16-byte read that the group's lanes share).  Keeping
+// them out of registers leaves the plane kernel at about 60 VGPRs.
 template <bool kBf16>
 struct OperandTable {
   typename MfmaTraits<kBf16>::vec fa[4][2][64];
   typename MfmaTraits<kBf16>::vec ia[4][2][64];
+  f32x4 qv[4][4], rq[4][4];
 };
 
-// Fills the lane's quantizer entries and (wave 0) the workgroup's operand table
-// (the inverse half only when kCodec); the caller synchronizes the workgroup after.
+// Fills (wave 0) the workgroup's operand table, the inverse half and the
+// quantizer entries only when kCodec; the caller synchronizes the workgroup after.
 template <bool kBf16, bool kCodec>
-__device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, OperandTable<kBf16> *inv, const FloatQuant &fq,
-                                           int wave, int i, int g) {
+__device__ __forceinline__ void kron_setup(OperandTable<kBf16> *inv, const FloatQuant &fq, int wave, int i, int g) {
   using T = MfmaTraits<kBf16>;
   typedef typename T::elem elem;
   const uint16_t *K = T::table();
   const int lane = 16 * g + i;
+  if (wave != 0) return;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -419,27 +416,28 @@ __device__ __forceinline__ void kron_setup(KronConsts<kBf16> &kc, OperandTable<k
         fa[e] = __builtin_bit_cast(elem, K[(16 * t + i) * 64 + sigma_index(s, g, e)]);
         if constexpr (kCodec) ia[e] = __builtin_bit_cast(elem, K[sigma_index(s, g, e) * 64 + 16 * t + i]);
       }
-      if (wave == 0) {
-        inv->fa[t][s][lane] = fa;
-        if constexpr (kCodec) inv->ia[t][s][lane] = ia;
-      }
+      inv->fa[t][s][lane] = fa;
+      if constexpr (kCodec) inv->ia[t][s][lane] = ia;
     }
   if constexpr (kCodec) {
-    // coefficient 16t + 4g + r has u + v = 2t + r + g/2 + 4(g%2)
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
+    if (i < 4) {
+      // lane (i < 4, g) fills entries t = i: coefficient 16t + 4g + r has u + v = 2t + r + g/2 + 4(g%2)
+      const int t = i;
+      f32x4 qq, rr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int sidx = 2 * t + r + (g >> 1) + 4 * (g & 1);
-        float qq = fq.Q[0], rr = fq.rcp[0];
+        qq[r] = fq.Q[0];
+        rr[r] = fq.rcp[0];
 #pragma unroll
         for (int k = 1; k < 15; ++k) {
-          qq = sidx == k ? fq.Q[k] : qq;
-          rr = sidx == k ? fq.rcp[k] : rr;
+          qq[r] = sidx == k ? fq.Q[k] : qq[r];
+          rr[r] = sidx == k ? fq.rcp[k] : rr[r];
         }
-        kc.qv[t][r] = qq;
-        kc.rq[t][r] = rr;
       }
+      inv->qv[t][g] = qq;
+      inv->rq[t][g] = rr;
+    }
   }
 }
 
@@ -486,21 +484,24 @@ __device__ __forceinline__ void kron_forward(const OperandTable<kBf16> *tab, int
 
 // quantize, dequantize, inverse product and reconstruction: the four output words
 template <bool kBf16>
-__device__ __forceinline__ void kron_code(const KronConsts<kBf16> &kc, const OperandTable<kBf16> *inv, int lane,
-                                          const f32x4 (&acc)[4], uint32_t (&rec)[4]) {
+__device__ __forceinline__ void kron_code(const OperandTable<kBf16> *inv, int lane, const f32x4 (&acc)[4],
+                                          uint32_t (&rec)[4]) {
   // the table is read afresh at every call: an opaque index keeps the compiler
   // from hoisting the reads out of the tile loop into registers
   asm volatile("" : "+v"(lane));
   using T = MfmaTraits<kBf16>;
   typedef typename T::vec vec;
   typedef typename T::elem elem;
+  const int g = lane >> 4;
   // element e = 4(t % 2) + r of inverse step t / 2
   vec bq[2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 4; ++t) {
+    const f32x4 qv = inv->qv[t][g], rq = inv->rq[t][g];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], kc.qv[t][r], kc.rq[t][r]));
+      bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], qv[r], rq[r]));
+  }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 x = T::mma(inv->ia[t][0][lane], bq[0], f32x4{128.0f, 128.0f, 128.0f, 128.0f});
@@ -546,62 +547,70 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
                                                               unsigned long long *__restrict__ sse) {
   const int wave = wave_index(), l = threadIdx.x & 63, i = l & 15, g = l >> 4;
   __shared__ OperandTable<kBf16> inv;
-  KronConsts<kBf16> kc;
-  kron_setup<kBf16, kCodec>(kc, &inv, fq, wave, i, g);
+  kron_setup<kBf16, kCodec>(&inv, fq, wave, i, g);
   __syncthreads();
   uint64_t err = 0;
-  // each wave walks its tiles with the words of the next kKronDepth tiles in flight
+  // Each wave walks its tiles with the words of the next kKronDepth tiles in
+  // flight, in a ring of kKronDepth + 1 slots that the unrolled loop rotates: no
+  // register of a load in flight is copied, which would wait for the load.  A
+  // tile's block positions are found once, when its words are loaded.
+  constexpr int kSlots = kKronDepth + 1;
   const int step = gridDim.x * kMfmaWaves;
   int tile = blockIdx.x * kMfmaWaves + wave;
-  // (the position of each tile's blocks is found once, when its words are loaded)
-  uint32_t ring[kKronDepth][4];
-  BlockPos rpos[kKronDepth];
+  uint32_t ring[kSlots][4];
+  BlockPos rpos[kSlots];
+  // The prefetch is four unconditional buffer loads per lane: the words of a block
+  // inside the image, and for every other lane the plane's first words (a load
+  // past the plane's bytes returns zero).  With no branch around the loads the
+  // compiler keeps them in flight until their tile is coded; an edge block
+  // reloads its words then, with edge replication.
+  const __amdgpu_buffer_rsrc_t plane =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(src), 0,
+                                        static_cast<int>(static_cast<uint32_t>(H - 1) * static_cast<uint32_t>(stride) +
+                                                         static_cast<uint32_t>(W)),
+                                        0x00020000);
+  auto fetch = [&](int t, uint32_t(&w)[4], BlockPos &p) {
+    p = tile_pos(t, i, W, H, bw, nblocks);
+    const uint32_t off = p.full ? static_cast<uint32_t>(p.by * 8 + (g >> 1)) * static_cast<uint32_t>(stride) +
+                                      static_cast<uint32_t>(p.bx * 8 + 4 * (g & 1))
+                                : 0u;
 #pragma unroll
-  for (int d = 0; d < kKronDepth; ++d) {
-    rpos[d] = tile_pos(tile + d * step, i, W, H, bw, nblocks);
+    for (int k = 0; k < 4; ++k)
+      w[k] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(
+          plane, static_cast<int>(off + static_cast<uint32_t>(2 * k * stride)), 0, 0));
+  };
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ring[d][k] = 0u;
-    if (tile + d * step < ntiles && rpos[d].live)
-      load_words(src, W, H, stride, rpos[d].by, rpos[d].bx, g, rpos[d].full, ring[d]);
-  }
-  for (; tile < ntiles; tile += step) {
-    const int b = tile * 16 + i;
-    const BlockPos p = rpos[0];
-    uint32_t w[4];
+  for (int d = 0; d < kKronDepth; ++d) fetch(tile + d * step, ring[d], rpos[d]);
+  while (tile < ntiles) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = ring[0][k];
+    for (int k = 0; k < kSlots; ++k) {
+      if (tile < ntiles) {
+        fetch(tile + kKronDepth * step, ring[(k + kKronDepth) % kSlots], rpos[(k + kKronDepth) % kSlots]);
+        uint32_t(&w)[4] = ring[k];
+        const BlockPos &p = rpos[k];
+        if (!p.full && p.live) load_words(src, W, H, stride, p.by, p.bx, g, false, w);
+        f32x4 acc[4];
+        kron_forward<kBf16>(&inv, l, w, acc);
+        if constexpr (!kCodec) {
+          if (p.live) {
+            const size_t b = static_cast<size_t>(tile) * 16 + i;
 #pragma unroll
-    for (int d = 0; d + 1 < kKronDepth; ++d) {
-      rpos[d] = rpos[d + 1];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) ring[d][k] = ring[d + 1][k];
-    }
-    {
-      const int tn = tile + kKronDepth * step;
-      BlockPos &pn = rpos[kKronDepth - 1];
-      pn = tile_pos(tn, i, W, H, bw, nblocks);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) ring[kKronDepth - 1][k] = 0u;
-      if (tn < ntiles && pn.live) load_words(src, W, H, stride, pn.by, pn.bx, g, pn.full, ring[kKronDepth - 1]);
-    }
-    f32x4 acc[4];
-    kron_forward<kBf16>(&inv, l, w, acc);
-    if constexpr (!kCodec) {
-      if (p.live) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          *reinterpret_cast<float4 *>(coef + static_cast<size_t>(b) * 64 + 16 * t + 4 * g) =
-              make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
-      }
-    } else {
-      uint32_t rec[4];
-      kron_code<kBf16>(kc, &inv, l, acc, rec);
-      if (p.full) {
-        store_words(dst, W, H, dst_stride, p.by, p.bx, g, true, rec);
-        err += words_sse_full(w, rec);
-      } else if (p.live) {
-        store_words(dst, W, H, dst_stride, p.by, p.bx, g, false, rec);
-        err += words_sse(w, rec, W, H, p.by, p.bx, g, false);
+            for (int t = 0; t < 4; ++t)
+              *reinterpret_cast<float4 *>(coef + b * 64 + 16 * t + 4 * g) =
+                  make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+          }
+        } else {
+          uint32_t rec[4];
+          kron_code<kBf16>(&inv, l, acc, rec);
+          if (p.full) {
+            store_words(dst, W, H, dst_stride, p.by, p.bx, g, true, rec);
+            err += words_sse_full(w, rec);
+          } else if (p.live) {
+            store_words(dst, W, H, dst_stride, p.by, p.bx, g, false, rec);
+            err += words_sse(w, rec, W, H, p.by, p.bx, g, false);
+          }
+        }
+        tile += step;
       }
     }
   }
@@ -684,8 +693,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
                                                                   unsigned long long *__restrict__ sse) {
   const int wave = wave_index(), l = threadIdx.x & 63, i = l & 15, g = l >> 4;
   __shared__ OperandTable<kBf16> inv;
-  KronConsts<kBf16> kc;
-  kron_setup<kBf16, true>(kc, &inv, fq, wave, i, g);
+  kron_setup<kBf16, true>(&inv, fq, wave, i, g);
   __syncthreads();
   uint64_t err[3] = {0, 0, 0};
   for (int tile = blockIdx.x * kMfmaWaves + wave; tile < ntiles; tile += gridDim.x * kMfmaWaves) {
@@ -698,7 +706,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
       f32x4 acc[4];
       kron_forward<kBf16>(&inv, l, w[c], acc);
       uint32_t rec[4];
-      kron_code<kBf16>(kc, &inv, l, acc, rec);
+      kron_code<kBf16>(&inv, l, acc, rec);
       if (p.live) {
         store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec);
         err[c] += words_sse(w[c], rec, W, H, p.by, p.bx, g, p.full);
