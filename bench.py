@@ -607,9 +607,9 @@ def bench_batch(args):
     side.wait_stream(torch.cuda.current_stream())
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(side):
-        batch.run(tune.grid, sse=sse)             # warm on the capture stream
+        batch.run(tune.grid, sse=sse, threads=tune.threads)             # warm on the capture stream
         with torch.cuda.graph(graph, stream=side):
-            batch.run(tune.grid, sse=sse)
+            batch.run(tune.grid, sse=sse, threads=tune.threads)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -657,9 +657,9 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic (generated on the device)",
         "config": {"workload": f"{n} grayscale images, W and H uniform on 64..4096, qs in {{2,4,8,16}}, "
                                f"fused codec R(10,12,12) in one graph-captured launch",
-                   "images": n, "gpixels": round(total_px / 1e9, 3), "chunk": tune.chunk, "grid": tune.grid,
-                   "entry_point": "dct_batch_run"},
-        "tuning_ms": {f"chunk{c}_grid{g}": round(v, 3) for (c, g), v in sorted(tune.table.items())},
+                   "images": n, "gpixels": round(total_px / 1e9, 3), "chunk": tune.chunk,
+                   "threads": tune.threads, "grid": tune.grid, "entry_point": "dct_batch_run_threads"},
+        "tuning_ms": {f"chunk{c}_threads{t}_grid{g}": round(v, 3) for (c, t, g), v in sorted(tune.table.items())},
         "per_image_launches": {"ms": round(ms_per, 3), "gpixel_s": round(total_px / (ms_per * 1e-3) / 1e9, 3),
                                "same_sse": same_sse},
         "parity": parity, "parity_images": len(sample),

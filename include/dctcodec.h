@@ -250,8 +250,8 @@ typedef struct {
  * graph and replayed:
  *
  * dct_batch_workspace_size: bytes of device workspace the batch needs with
- *   `chunk` blocks per workgroup (256 or 512); 0 if any image or argument is
- *   invalid.
+ *   `chunk` blocks per work item, the tile a workgroup codes at a time (256,
+ *   512, 1024 or 2048); 0 if any image or argument is invalid.
  * dct_batch_plan: validates the images (host array of n_images), writes the
  *   batch description into `workspace` (device memory, 256-byte aligned, at
  *   least the size above, owned by the caller), waits for `stream`, and
@@ -264,12 +264,18 @@ typedef struct {
  *   workgroups, each walking the chunks with a fixed stride.  Enqueues two
  *   kernels and nothing else, so it can be captured in a graph.  The images'
  *   planes must stay valid and unchanged in place between plan and run.
+ *   Each workgroup has min(chunk, 512) lanes, one block per lane.
  *   DCT_ERR_INVALID if the workspace holds no plan.
+ * dct_batch_run_threads: dct_batch_run with `threads` lanes per workgroup (256
+ *   or 512, at most the plan's chunk), which codes a chunk in chunk / threads
+ *   passes.  DCT_ERR_INVALID for another thread count.
  * dct_batch_release: forgets the plan of a workspace (the caller frees it). */
 DCT_API size_t dct_batch_workspace_size(const dct_image *images, int32_t n_images, int32_t chunk);
 DCT_API int dct_batch_plan(const dct_image *images, int32_t n_images, int32_t chunk, void *workspace,
                            size_t workspace_bytes, int64_t *total_chunks, void *stream);
 DCT_API int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *stream);
+DCT_API int dct_batch_run_threads(const void *workspace, int32_t grid, int32_t threads, uint64_t *sse_dev,
+                                  void *stream);
 DCT_API int dct_batch_release(const void *workspace);
 
 /* Learned deblocking post-filter for decoded planes.  The paper's decoded images

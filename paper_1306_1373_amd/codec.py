@@ -60,6 +60,7 @@ _PROTOS = {
     "dct_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_int64), C.c_void_p]),
     "dct_batch_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dct_batch_run_threads": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "dct_batch_release": (C.c_int, [C.c_void_p]),
     "dct_deblock_nparam": (C.c_int32, []),
     "dct_deblock_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
@@ -393,10 +394,15 @@ class Batch:
         self.sse = torch.zeros(n, dtype=torch.int64, device=dev)
         self._keep = (list(srcs), list(dsts))
 
-    def run(self, grid: int = 0, sse=None):
-        """Code the batch; returns the int64 device tensor of per-image SSEs."""
+    def run(self, grid: int = 0, sse=None, threads: int = None):
+        """Code the batch (threads lanes per workgroup: None for min(chunk, 512));
+        returns the int64 device tensor of per-image SSEs."""
         out = self.sse if sse is None else sse
-        _check(load().dct_batch_run(self._ws_ptr, int(grid), out.data_ptr(), _stream(out)), "dct_batch_run")
+        if threads is None:
+            _check(load().dct_batch_run(self._ws_ptr, int(grid), out.data_ptr(), _stream(out)), "dct_batch_run")
+        else:
+            _check(load().dct_batch_run_threads(self._ws_ptr, int(grid), int(threads), out.data_ptr(), _stream(out)),
+                   "dct_batch_run_threads")
         return out
 
     def release(self):

@@ -27,7 +27,7 @@ struct BatchPlan {
 };
 std::unordered_map<const void *, BatchPlan> g_batches;  // guarded by lock()
 
-bool chunk_ok(int chunk) { return chunk == 256 || chunk == 512; }
+bool chunk_ok(int chunk) { return chunk == 256 || chunk == 512 || chunk == 1024 || chunk == 2048; }
 
 // Chunks of each image and the workspace layout; false if an image is invalid.
 bool batch_layout(const dct_image *images, int32_t n, int32_t chunk, BatchPlan &plan, size_t &bytes) {
@@ -103,8 +103,10 @@ int dct_batch_plan(const dct_image *images, int32_t n_images, int32_t chunk, voi
   return DCT_OK;
 }
 
-int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *stream) {
-  if (workspace == nullptr || sse_dev == nullptr || !aligned(sse_dev, 8) || grid < 0) return DCT_ERR_INVALID;
+int dct_batch_run_threads(const void *workspace, int32_t grid, int32_t threads, uint64_t *sse_dev, void *stream) {
+  if (workspace == nullptr || sse_dev == nullptr || !aligned(sse_dev, 8) || grid < 0 ||
+      (threads != 256 && threads != 512))
+    return DCT_ERR_INVALID;
   BatchPlan plan{};
   {
     std::lock_guard<std::mutex> guard(lock());
@@ -112,6 +114,7 @@ int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *
     if (it == g_batches.end()) return DCT_ERR_INVALID;
     plan = it->second;
   }
+  if (threads > plan.chunk) return DCT_ERR_INVALID;
   if (int st = check_device(nullptr)) return st;
   hipStream_t s = as_stream(stream);
   auto *acc = reinterpret_cast<unsigned long long *>(sse_dev);
@@ -121,11 +124,23 @@ int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *
   const auto *imgs = reinterpret_cast<const dct::BatchImage *>(base + plan.images_offset);
   const auto *table = reinterpret_cast<const int32_t *>(base + plan.table_offset);
   const unsigned g = static_cast<unsigned>(grid == 0 ? plan.total_chunks : std::min<int64_t>(grid, plan.total_chunks));
-  if (plan.chunk == 512)
-    dct::batch_codec_kernel<512><<<g, 512, 0, s>>>(imgs, table, plan.total_chunks, acc);
+  if (threads == 512)
+    dct::batch_codec_kernel<512><<<g, 512, 0, s>>>(imgs, table, plan.total_chunks, plan.chunk, acc);
   else
-    dct::batch_codec_kernel<256><<<g, 256, 0, s>>>(imgs, table, plan.total_chunks, acc);
+    dct::batch_codec_kernel<256><<<g, 256, 0, s>>>(imgs, table, plan.total_chunks, plan.chunk, acc);
   return launched();
+}
+
+int dct_batch_run(const void *workspace, int32_t grid, uint64_t *sse_dev, void *stream) {
+  if (workspace == nullptr) return DCT_ERR_INVALID;
+  int32_t chunk = 0;
+  {
+    std::lock_guard<std::mutex> guard(lock());
+    auto it = g_batches.find(workspace);
+    if (it == g_batches.end()) return DCT_ERR_INVALID;
+    chunk = it->second.chunk;
+  }
+  return dct_batch_run_threads(workspace, grid, std::min(chunk, 512), sse_dev, stream);
 }
 
 int dct_batch_release(const void *workspace) {

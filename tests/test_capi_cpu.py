@@ -180,7 +180,9 @@ def test_batch_struct_and_validation(lib):
     ok = codec.DctImage(4096, 8192, 16, 8, 16, 16, 4, 0)
     arr = (codec.DctImage * 2)(ok, ok)
     assert lib.dct_batch_workspace_size(arr, 2, 512) > 256
-    assert lib.dct_batch_workspace_size(arr, 2, 300) == 0        # chunk must be 256 or 512
+    assert lib.dct_batch_workspace_size(arr, 2, 300) == 0        # chunk must be 256, 512, 1024 or 2048
+    assert lib.dct_batch_workspace_size(arr, 2, 4096) == 0
+    assert lib.dct_batch_workspace_size(arr, 2, 2048) > 256
     assert lib.dct_batch_workspace_size(arr, 0, 512) == 0
     assert lib.dct_batch_workspace_size(None, 2, 512) == 0
     bad = (codec.DctImage * 1)(codec.DctImage(4096, 8192, 16, 8, 16, 16, 0, 0))   # qs = 0
@@ -193,6 +195,9 @@ def test_batch_struct_and_validation(lib):
     assert lib.dct_batch_plan(arr, 2, 512, C.c_void_p((1 << 20) + 8), 1 << 20, C.byref(n), None) == \
         codec.DCT_ERR_INVALID
     assert lib.dct_batch_run(C.c_void_p(1 << 20), 0, C.c_void_p(4096), None) == codec.DCT_ERR_INVALID
+    for threads in (128, 256, 1024):      # no plan (and 128 / 1024 lanes are never valid)
+        assert lib.dct_batch_run_threads(C.c_void_p(1 << 20), 0, threads, C.c_void_p(4096), None) == \
+            codec.DCT_ERR_INVALID
     assert lib.dct_batch_release(C.c_void_p(1 << 20)) == codec.DCT_ERR_INVALID
 
 
@@ -205,6 +210,8 @@ def test_batch_layout_sizes(lib):
     size = lib.dct_batch_workspace_size(arr, 3, 512)
     img_bytes = -(-3 * 240 // 256) * 256
     assert size == 256 + img_bytes + 4 * chunks
+    chunks2048 = 1 + 1 + 1                # every image fits one 2048-block tile
+    assert lib.dct_batch_workspace_size(arr, 3, 2048) == 256 + img_bytes + 4 * chunks2048
 
 
 def test_deblock_abi_validation(lib):

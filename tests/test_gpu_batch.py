@@ -60,13 +60,17 @@ def check(oracle_mod, imgs, dsts, qs, sse):
         assert int(sse[k]) == s, k
 
 
-@pytest.mark.parametrize("chunk,grid", [(512, 0), (256, 0), (512, 3), (256, 7)])
-def test_batch_bit_exact(hip, oracle_mod, chunk, grid):
+@pytest.mark.parametrize("chunk,threads,grid", [(512, None, 0), (256, None, 0), (512, None, 3), (256, None, 7),
+                                               (1024, 256, 0), (2048, 512, 5), (1024, 512, 0), (512, 256, 9)])
+def test_batch_bit_exact(hip, oracle_mod, chunk, threads, grid):
+    # every tile size and workgroup size: a workgroup of `threads` lanes codes a
+    # tile of `chunk` blocks in chunk / threads passes
     imgs, srcs, dsts, qs = make_batch(40, 90 + chunk + grid)
     batch = hip.Batch(srcs, dsts, qs, chunk=chunk)
-    sse = batch.run(grid)
+    sse = batch.run(grid, threads=threads)
     check(oracle_mod, imgs, dsts, qs, sse)
-    say(f"[gpu] batch chunk {chunk} grid {grid}: {batch.total_chunks} chunks, {len(imgs)} images exact")
+    say(f"[gpu] batch chunk {chunk} threads {threads} grid {grid}: {batch.total_chunks} chunks, "
+        f"{len(imgs)} images exact")
     batch.release()
 
 
@@ -116,7 +120,10 @@ def test_unplanned_workspace_rejected(hip):
     assert hip.load().dct_batch_run(C.c_void_p(ws.data_ptr()), 0, C.c_void_p(sse.data_ptr()), None) == \
         hip.DCT_ERR_INVALID
     imgs, srcs, dsts, qs = make_batch(5, 3)
-    batch = hip.Batch(srcs, dsts, qs)
+    batch = hip.Batch(srcs, dsts, qs, chunk=256)
+    for bad in (128, 512, 1024):          # not 256 or 512, or more lanes than the tile
+        with pytest.raises(hip.DctError):
+            batch.run(threads=bad)
     batch.release()
     with pytest.raises(hip.DctError):
         batch.run()
@@ -126,7 +133,7 @@ def test_tuner_returns_a_measured_configuration(hip, oracle_mod):
     from paper_1306_1373_amd.autotune import tune_batch
     imgs, srcs, dsts, qs = make_batch(30, 17, max_side=900)
     res, batch = tune_batch(srcs, dsts, qs, grids=(0, 64, 512), reps=2)
-    assert (res.chunk, res.grid) in res.table and res.ms == min(res.table.values())
-    assert len(res.table) == 6
-    sse = batch.run(res.grid)
+    assert (res.chunk, res.threads, res.grid) in res.table and res.ms == min(res.table.values())
+    assert len(res.table) == 21         # tiles 256: one lane count; 512, 1024, 2048: two; three grids each
+    sse = batch.run(res.grid, threads=res.threads)
     check(oracle_mod, imgs, dsts, qs, sse)
