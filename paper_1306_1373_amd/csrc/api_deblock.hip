@@ -23,8 +23,8 @@ using namespace dct::host;
 constexpr int kGradGroups = 2048;
 // chunks (32 pixels of a row) per workgroup of the 32 -> 32 weight-gradient pass
 // and of the layer 1 / layer 4 passes
-constexpr int kMidChunks = 4;
-constexpr int kEdgeChunks = 16;
+constexpr int kMidChunks = 8;
+constexpr int kEdgeChunks = 8;
 // workgroups of the training output layer (each writes one partial loss sum)
 constexpr int kLossGroups = 1024;
 
@@ -286,27 +286,32 @@ int deblock_backward(const dct::db::ImageSet &set, int64_t npix, uint8_t *ws, co
   };
   const uint32_t cpw_mid = per_group(kMidChunks), cpw_edge = per_group(kEdgeChunks);
   const unsigned wg_mid = (nchunks + cpw_mid - 1) / cpw_mid, wg_edge = (nchunks + cpw_edge - 1) / cpw_edge;
-  auto reduce = [&](unsigned nwg, int nw, int nb, float *dW, float *db, float wscale) {
-    reduce_kernel<<<static_cast<unsigned>((nw + nb + 63) / 64), kThreads, 0, s>>>(part, static_cast<int>(nwg), nw,
-                                                                                   nb, dW, db, wscale, inv_s);
+  auto reduce = [&](bool mid_rows, unsigned nwg, int nw, int nb, float *dW, float *db, float wscale) {
+    const unsigned grid = static_cast<unsigned>((nw + nb + 63) / 64);
+    if (mid_rows)
+      reduce_kernel<true><<<grid, 64 * kRedWaves, 0, s>>>(part, static_cast<int>(nwg), nw, nb, dW, db, wscale,
+                                                          inv_s);
+    else
+      reduce_kernel<false><<<grid, 64 * kRedWaves, 0, s>>>(part, static_cast<int>(nwg), nw, nb, dW, db, wscale,
+                                                           inv_s);
   };
   const int64_t ntiles = static_cast<int64_t>(set.n) * ((set.h + kRows - 1) / kRows) * ((set.w + 15) / 16);
   const unsigned mgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + 3) / 4, 8192));
   // layer 4
-  wgrad_edge_kernel<false><<<wg_edge, 64, 0, s>>>(set, a3, g4, part, nchunks, cpw_edge);
-  reduce(wg_edge, kC * 9, 1, grad + kW4, grad + kB4, inv_s);
+  wgrad_edge_kernel<false><<<wg_edge, kEdgeGradThreads, 0, s>>>(set, a3, g4, part, nchunks, cpw_edge);
+  reduce(false, wg_edge, kC * 9, 1, grad + kW4, grad + kB4, inv_s);
   bwd4_kernel<<<px_grid(npix), kThreads, 0, s>>>(set, g4, a3, wq, ga, npix);
   // layer 3: ga = S dL/d(pre-activation 3)
-  wgrad_mid_kernel<<<wg_mid, 192, 0, s>>>(set, ga, a2, part, nchunks, cpw_mid);
-  reduce(wg_mid, kC * kC * 9, kC, grad + kW3, grad + kB3, inv_s);
+  wgrad_mid_kernel<<<wg_mid, kMidGradThreads, 0, s>>>(set, ga, a2, part, nchunks, cpw_mid);
+  reduce(true, wg_mid, kC * kC * 9, kC, grad + kW3, grad + kB3, inv_s);
   mid_kernel<true><<<mgrid, kThreads, 0, s>>>(set, ga, wh + kW3, nullptr, a2, gb, npix, ntiles);
   // layer 2
-  wgrad_mid_kernel<<<wg_mid, 192, 0, s>>>(set, gb, a1, part, nchunks, cpw_mid);
-  reduce(wg_mid, kC * kC * 9, kC, grad + kW2, grad + kB2, inv_s);
+  wgrad_mid_kernel<<<wg_mid, kMidGradThreads, 0, s>>>(set, gb, a1, part, nchunks, cpw_mid);
+  reduce(true, wg_mid, kC * kC * 9, kC, grad + kW2, grad + kB2, inv_s);
   mid_kernel<true><<<mgrid, kThreads, 0, s>>>(set, gb, wh + kW2, nullptr, a1, ga, npix, ntiles);
   // layer 1: the pixel values' 1/255 joins the scale of the weight gradients
-  wgrad_edge_kernel<true><<<wg_edge, 64, 0, s>>>(set, ga, nullptr, part, nchunks, cpw_edge);
-  reduce(wg_edge, kC * 9, kC, grad + kW1, grad + kB1, inv_s * kInv255);
+  wgrad_edge_kernel<true><<<wg_edge, kEdgeGradThreads, 0, s>>>(set, ga, nullptr, part, nchunks, cpw_edge);
+  reduce(false, wg_edge, kC * 9, kC, grad + kW1, grad + kB1, inv_s * kInv255);
   return launched();
 }
 

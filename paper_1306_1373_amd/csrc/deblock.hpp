@@ -566,9 +566,37 @@ __global__ __launch_bounds__(kThreads) void bwd4_kernel(ImageSet s, const _Float
 // supplies pixels c0 + 8g .. c0 + 8g + 7 of the chunk to both operands of
 // v_mfma_f32_16x16x32_f16, whose D[4g + r][j] it then holds.  Workgroup w takes
 // chunks w cpw .. w cpw + cpw - 1 and writes one partial row of FP32 sums (of the
-// scaled signals) to part[w]; reduce_kernel adds the rows.
+// scaled signals) to part[w]; reduce_kernel adds the rows.  A 32 -> 32 layer's
+// row holds its weights in accumulator order (mid_slot), so that each of a
+// wave's stores covers 64 consecutive floats; reduce_kernel puts them back in
+// the [co][ci][t] order of the parameters.
 inline constexpr int kNWMid = kC * kC * 9 + kC;  // partial row of a 32 -> 32 layer
 inline constexpr int kNWEdge = kC * 9 + kC;      // partial row of layer 1 (layer 4 uses 9 kC + 1)
+
+// Slot of D[4 gq + r][j] of tile (m, n) of tap t in a 32 -> 32 layer's partial
+// row, and the weight (co, ci, t) = (16 m + 4 gq + r, 16 n + j, t) it belongs to.
+__host__ __device__ constexpr int mid_slot(int t, int m, int n, int r, int gq, int j) {
+  return ((((t * 2 + m) * 2 + n) * 4 + r) * 4 + gq) * 16 + j;
+}
+__host__ __device__ constexpr int mid_weight_of_slot(int k) {
+  const int j = k & 15, gq = (k >> 4) & 3, r = (k >> 6) & 3, n = (k >> 8) & 1, m = (k >> 9) & 1, t = k >> 10;
+  return ((16 * m + 4 * gq + r) * kC + 16 * n + j) * 9 + t;
+}
+constexpr bool mid_slots_invert() {
+  for (int t = 0; t < 9; ++t)
+    for (int m = 0; m < 2; ++m)
+      for (int n = 0; n < 2; ++n)
+        for (int r = 0; r < 4; ++r)
+          for (int gq = 0; gq < 4; ++gq)
+            for (int j = 0; j < 16; ++j) {
+              const int k = mid_slot(t, m, n, r, gq, j);
+              if (k < 0 || k >= kC * kC * 9 ||
+                  mid_weight_of_slot(k) != ((16 * m + 4 * gq + r) * kC + 16 * n + j) * 9 + t)
+                return false;
+            }
+  return true;
+}
+static_assert(mid_slots_invert(), "mid_slot is a bijection onto the weights, undone by mid_weight_of_slot");
 
 struct Chunk {
   int b, r, c;  // image, row, first column of this lane's eight pixels
@@ -587,13 +615,20 @@ __device__ __forceinline__ Chunk chunk_of(const ImageSet &s, uint32_t chunk, int
 // 32 -> 32 layer: dW[co][ci][t] = sum_p g[p][co] a[p + offset(t)][ci], db[co] = sum_p g[p][co]
 // (g the scaled FP16 signal of the layer's pre-activation, a its FP16 input).
 // A[j][8g+e] = g[pixel e][16m + j], B[8g+e][j] = a[pixel e + offset(t)][16n + j].
-// Three waves per workgroup; wave dy computes the taps (dy, 0..2) for all four
+// Three waves per chunk stream; wave dy computes the taps (dy, 0..2) for all four
 // 16 x 16 (co, ci) tiles: the ten input pixels c - 1 .. c + 8 of its tap row give
-// the three column offsets' operands.  Wave 0 also sums the bias gradients.
-__global__ __launch_bounds__(192) void wgrad_mid_kernel(ImageSet s, const _Float16 *__restrict__ g,
-                                                         const _Float16 *__restrict__ a, float *__restrict__ part,
-                                                         uint32_t nchunks, uint32_t cpw) {
-  const int dy = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+// the three column offsets' operands.  Wave 0 of a stream also sums the bias
+// gradients.  A workgroup runs kMidSplit streams, stream h taking every kMidSplit-th
+// of its chunks from the h-th on; the other streams' sums are added to stream 0's
+// through LDS in stream order, so the partial row does not depend on timing.
+inline constexpr int kMidSplit = 2;
+inline constexpr int kMidGradThreads = 3 * 64 * kMidSplit;
+__global__ __launch_bounds__(kMidGradThreads) void wgrad_mid_kernel(ImageSet s, const _Float16 *__restrict__ g,
+                                                                     const _Float16 *__restrict__ a,
+                                                                     float *__restrict__ part, uint32_t nchunks,
+                                                                     uint32_t cpw) {
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int dy = wave % 3, stream = wave / 3;
   const int l = threadIdx.x & 63, j = l & 15, gq = l >> 4;
   f4 acc[3][2][2];
 #pragma unroll
@@ -605,7 +640,7 @@ __global__ __launch_bounds__(192) void wgrad_mid_kernel(ImageSet s, const _Float
   float bsum[2] = {0.0f, 0.0f};
   const uint32_t first = blockIdx.x * cpw, last = min(first + cpw, nchunks);
   const _Float16 zero = static_cast<_Float16>(0.0f);
-  for (uint32_t chunk = first; chunk < last; ++chunk) {
+  for (uint32_t chunk = first + stream; chunk < last; chunk += kMidSplit) {
     const Chunk k = chunk_of(s, chunk, gq);
     const int64_t row = static_cast<int64_t>(k.b) * s.h + k.r;
     h8 A[2];
@@ -642,6 +677,37 @@ __global__ __launch_bounds__(192) void wgrad_mid_kernel(ImageSet s, const _Float
       }
     }
   }
+  // [stream - 1][dy][value][lane]: 48 accumulator values, then the two bias sums
+  __shared__ float other[kMidSplit - 1][3][50][64];
+  if (stream > 0) {
+    float *o = &other[stream - 1][dy][0][l];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[64 * (((dx * 2 + m) * 2 + n) * 4 + r)] = acc[dx][m][n][r];
+    o[64 * 48] = bsum[0];
+    o[64 * 49] = bsum[1];
+  }
+  __syncthreads();
+  if (stream > 0) return;
+#pragma unroll
+  for (int h = 0; h < kMidSplit - 1; ++h) {
+    const float *o = &other[h][dy][0][l];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[dx][m][n][r] += o[64 * (((dx * 2 + m) * 2 + n) * 4 + r)];
+    bsum[0] += o[64 * 48];
+    bsum[1] += o[64 * 49];
+  }
   float *dst = part + static_cast<size_t>(blockIdx.x) * kNWMid;
 #pragma unroll
   for (int dx = 0; dx < 3; ++dx)
@@ -651,7 +717,7 @@ __global__ __launch_bounds__(192) void wgrad_mid_kernel(ImageSet s, const _Float
       for (int n = 0; n < 2; ++n)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          dst[((16 * m + 4 * gq + r) * kC + 16 * n + j) * 9 + dy * 3 + dx] = acc[dx][m][n][r];
+          dst[mid_slot(dy * 3 + dx, m, n, r, gq, j)] = acc[dx][m][n][r];
   if (dy == 0) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
@@ -671,19 +737,25 @@ __global__ __launch_bounds__(192) void wgrad_mid_kernel(ImageSet s, const _Float
 //           applies the 1/255 of x = P / 255);
 //   else:   dW4[ci][t] = sum_q a3[q][ci] g4[q - offset(t)], db4 = sum_q g4[q],
 //           A[j][8g+e] = a3[pixel e][16m + j], B[8g+e][t] = g4[pixel e - offset(t)].
-// One wave per workgroup.
+// kEdgeSplit waves per workgroup, wave h taking every kEdgeSplit-th of its chunks
+// from the h-th on; the other waves' sums are added to wave 0's through LDS in
+// wave order.
+inline constexpr int kEdgeSplit = 4;
+inline constexpr int kEdgeGradThreads = 64 * kEdgeSplit;
 template <bool kFirst>
-__global__ __launch_bounds__(64) void wgrad_edge_kernel(ImageSet s, const _Float16 *__restrict__ act,
-                                                         const _Float16 *__restrict__ g4, float *__restrict__ part,
-                                                         uint32_t nchunks, uint32_t cpw) {
+__global__ __launch_bounds__(kEdgeGradThreads) void wgrad_edge_kernel(ImageSet s, const _Float16 *__restrict__ act,
+                                                                       const _Float16 *__restrict__ g4,
+                                                                       float *__restrict__ part, uint32_t nchunks,
+                                                                       uint32_t cpw) {
   constexpr int NW = kFirst ? kNWEdge : kC * 9 + 1;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int l = threadIdx.x & 63, j = l & 15, gq = l >> 4;
   const int tdy = j / 3 - 1, tdx = j % 3 - 1;  // this lane's tap offset (j < 9)
   f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
   float bsum[2] = {0.0f, 0.0f};
   const uint32_t first = blockIdx.x * cpw, last = min(first + cpw, nchunks);
   const _Float16 zero = static_cast<_Float16>(0.0f);
-  for (uint32_t chunk = first; chunk < last; ++chunk) {
+  for (uint32_t chunk = first + wave; chunk < last; chunk += kEdgeSplit) {
     const Chunk k = chunk_of(s, chunk, gq);
     const int64_t row = static_cast<int64_t>(k.b) * s.h + k.r;
     h8 A[2], B;
@@ -717,6 +789,23 @@ __global__ __launch_bounds__(64) void wgrad_edge_kernel(ImageSet s, const _Float
 #pragma unroll
     for (int m = 0; m < 2; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[m], B, acc[m], 0, 0, 0);
   }
+  // [wave - 1][value][lane]: eight accumulator values, then the two bias sums
+  __shared__ float other[kEdgeSplit - 1][10][64];
+  if (wave > 0) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) other[wave - 1][v][l] = acc[v >> 2][v & 3];
+    other[wave - 1][8][l] = bsum[0];
+    other[wave - 1][9][l] = bsum[1];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int h = 0; h < kEdgeSplit - 1; ++h) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[v >> 2][v & 3] += other[h][v][l];
+    bsum[0] += other[h][8][l];
+    bsum[1] += other[h][9][l];
+  }
   float *dst = part + static_cast<size_t>(blockIdx.x) * NW;
   if (j < 9) {
 #pragma unroll
@@ -743,13 +832,17 @@ __global__ __launch_bounds__(64) void wgrad_edge_kernel(ImageSet s, const _Float
 
 // Second stage: dW[k] = wscale * (sum over workgroups of part[w][k]) for the nw
 // weights, db[k] likewise with bscale for the nb biases stored after them.  A
-// workgroup reduces 64 consecutive entries; its four waves take every fourth
-// partial row each (the loads of a lane are independent, so many are in flight),
-// then add their four sums in LDS: a fixed order, so the result is deterministic.
-__global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restrict__ part, int nwg, int nw, int nb,
-                                                          float *__restrict__ dW, float *__restrict__ db,
-                                                          float wscale, float bscale) {
-  constexpr int kWaves = kThreads / 64;
+// workgroup reduces 64 consecutive entries; its kRedWaves waves take every
+// kRedWaves-th partial row each (the loads of a lane are independent, so many are
+// in flight), then add their sums in LDS: a fixed order, so the result is
+// deterministic.
+// kMidRows: the rows hold a 32 -> 32 layer's weights in mid_slot order.
+inline constexpr int kRedWaves = 16;
+template <bool kMidRows>
+__global__ __launch_bounds__(64 * kRedWaves) void reduce_kernel(const float *__restrict__ part, int nwg, int nw,
+                                                                int nb, float *__restrict__ dW,
+                                                                float *__restrict__ db, float wscale, float bscale) {
+  constexpr int kWaves = kRedWaves;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = nw + nb;
   const int k = blockIdx.x * 64 + lane;
@@ -766,7 +859,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const float *__restric
 #pragma unroll
     for (int j = 0; j < kWaves; ++j) t += sums[j][lane];
     if (k < nw)
-      dW[k] = t * wscale;
+      dW[kMidRows ? mid_weight_of_slot(k) : k] = t * wscale;
     else
       db[k - nw] = t * bscale;
   }
