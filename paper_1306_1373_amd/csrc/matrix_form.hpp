@@ -128,6 +128,18 @@ __device__ __forceinline__ float fquant(float F, float Q, float rcp) {
   return __builtin_copysignf(q, F) * Q;
 }
 
+// The matrix form's quantizer in three instructions: t = F (1/Q) + 1.5 2^23 (one
+// FMA) lies in [2^23, 2^24), where the last place is 1, so t holds 1.5 2^23 + q
+// with q the integer nearest the exact product F (1/Q) (ties to even, either
+// sign; needs |F / Q| < 2^22, which |F| <= 1024 gives); t - 1.5 2^23 = q and
+// q Q (< 2^24) are exact.  It differs from sgn(F) floor(|F| / Q + 1/2) only when
+// the product is an exact half-integer, within the form's error of the rounding
+// boundary.
+inline constexpr float kRoundMagic = 12582912.0f;  // 1.5 2^23
+__device__ __forceinline__ float fquant_rne(float F, float rcp, float Q) {
+  return (__builtin_fmaf(F, rcp, kRoundMagic) - kRoundMagic) * Q;
+}
+
 // clamp(floor(x + 128 + 1/2), 0, 255)
 __device__ __forceinline__ uint32_t freconstruct(float x) {
   const float p = __builtin_floorf(x + 128.5f);
@@ -327,6 +339,8 @@ __device__ __forceinline__ void load_words(const uint8_t *__restrict__ src, int 
   }
 }
 
+// the same for stores; a block inside the image is stored non-temporally (its
+// bytes are not read again), an edge block byte by byte
 __device__ __forceinline__ void store_words(uint8_t *__restrict__ dst, int W, int H, int stride, int by, int bx,
                                             int g, bool full, const uint32_t (&w)[4]) {
   const int x0 = bx * 8 + 4 * (g & 1), y0 = by * 8 + (g >> 1);
@@ -334,7 +348,7 @@ __device__ __forceinline__ void store_words(uint8_t *__restrict__ dst, int W, in
     const uint32_t off = static_cast<uint32_t>(y0) * static_cast<uint32_t>(stride) + static_cast<uint32_t>(x0);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-      *reinterpret_cast<uint32_t *>(dst + (off + static_cast<uint32_t>(2 * t * stride))) = w[t];
+      __builtin_nontemporal_store(w[t], reinterpret_cast<uint32_t *>(dst + (off + static_cast<uint32_t>(2 * t * stride))));
   } else {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -500,7 +514,7 @@ __device__ __forceinline__ void kron_code(const OperandTable<kBf16> *inv, int la
     const f32x4 qv = inv->qv[t][g], rq = inv->rq[t][g];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant(acc[t][r], qv[r], rq[r]));
+      bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant_rne(acc[t][r], rq[r], qv[r]));
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -563,7 +577,9 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
   // inside the image, and for every other lane the plane's first words (a load
   // past the plane's bytes returns zero).  With no branch around the loads the
   // compiler keeps them in flight until their tile is coded; an edge block
-  // reloads its words then, with edge replication.
+  // reloads its words then, with edge replication.  The loads (cache policy 2)
+  // and the stores of whole blocks are non-temporal: every byte of the planes is
+  // read once and written once.
   const __amdgpu_buffer_rsrc_t plane =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(src), 0,
                                         static_cast<int>(static_cast<uint32_t>(H - 1) * static_cast<uint32_t>(stride) +
@@ -577,7 +593,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       w[k] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(
-          plane, static_cast<int>(off + static_cast<uint32_t>(2 * k * stride)), 0, 0));
+          plane, static_cast<int>(off + static_cast<uint32_t>(2 * k * stride)), 0, 2));
   };
 #pragma unroll
   for (int d = 0; d < kKronDepth; ++d) fetch(tile + d * step, ring[d], rpos[d]);
