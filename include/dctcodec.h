@@ -368,6 +368,16 @@ DCT_API int dct_recipe_info(int32_t *n_iter, int32_t *frac_bits, int32_t *comp_b
  *               of the even rotation), and round(sqrt(2) 2^P). */
 DCT_API int dct_recipe_tables(int32_t *directions, int32_t *gains);
 
+/* Not an operation of the codec, a measurement aid: copies `bytes` bytes from
+ * src to dst (device, 16-byte aligned, not overlapping; bytes a non-negative
+ * multiple of 16), one 16-byte word per lane with non-temporal loads and stores,
+ * enqueued on `stream`.  Timed, it gives the HBM bandwidth that a pure
+ * read-once, write-once stream reaches, the practical ceiling beside which the
+ * codec kernels' bandwidth is read.  DCT_ERR_INVALID for a null, misaligned or
+ * overlapping buffer or a bad size; 0 bytes is DCT_OK with nothing enqueued,
+ * whatever the pointers. */
+DCT_API int dct_probe_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
 /* Human-readable name of a dct_status value (static storage). */
 DCT_API const char *dct_status_string(int status);
 

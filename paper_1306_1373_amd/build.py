@@ -20,7 +20,7 @@ OBJ_DIR = os.path.join(PKG, "_build")
 # several sources because its kernel instantiations dominate the build
 SOURCES = [os.path.join(CSRC, f) for f in ("api_core.hip", "api_codec.hip", "recipes_n4_n6.hip",
                                            "recipes_n8_n10.hip", "recipes_n12.hip", "api_float.hip",
-                                           "api_batch.hip", "api_deblock.hip")]
+                                           "api_batch.hip", "api_deblock.hip", "api_probe.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "transform.hpp", "recipe.hpp", "matrix_form.hpp",
                                            "batch.hpp", "deblock.hpp", "staged.hpp", "host.hpp", "rows.hpp",
                                            "codec_launch.hpp")] + [

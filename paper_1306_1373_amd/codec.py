@@ -82,6 +82,7 @@ _PROTOS = {
                                    C.c_void_p, C.c_void_p]),
     "dct_recipe_info": (C.c_int, [C.POINTER(C.c_int32)] * 3),
     "dct_recipe_tables": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "dct_probe_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "dct_status_string": (C.c_char_p, [C.c_int]),
     "dct_shutdown": (C.c_int, []),
 }
@@ -592,6 +593,20 @@ def recipe_list():
 
 def recipe_supported(n: int, F: int, G: int) -> bool:
     return bool(load().dct_recipe_supported(int(n), int(F), int(G)))
+
+
+def probe_copy(src, dst):
+    """Measurement aid, not an operation of the codec: copies the bytes of the
+    contiguous device tensor src into dst (same byte count, 16-byte aligned, a
+    multiple of 16 bytes) with the library's plain non-temporal copy, on the
+    current stream.  Timed, it gives the HBM bandwidth a pure stream reaches."""
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous device tensor")
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("src and dst differ in size")
+    _check(load().dct_probe_copy(src.data_ptr(), dst.data_ptr(), n, _stream(src)), "dct_probe_copy")
 
 
 def status_string(status: int) -> str:

@@ -224,3 +224,21 @@ def test_deblock_abi_validation(lib):
         codec.DCT_ERR_INVALID                                                               # n > 1 needs pos
     assert lib.dct_deblock_adam(P16, P16, P16, P16, 0, 1e-3, 0.9, 0.999, 1e-8, None) == codec.DCT_ERR_INVALID
     assert lib.dct_deblock_adam(P16, P16, P16, P16, 1, 1e-3, 1.0, 0.999, 1e-8, None) == codec.DCT_ERR_INVALID
+
+
+@pytest.mark.parametrize("src,dst,nbytes", [
+    (None, P16, 64),                    # null source
+    (P16, None, 64),                    # null destination
+    (MIS, P16, 64),                     # misaligned source
+    (P16, C.c_void_p(8200), 64),        # destination 8-byte aligned only
+    (P16, C.c_void_p(1 << 20), -16),    # negative size
+    (P16, C.c_void_p(1 << 20), 24),     # not a multiple of 16
+    (P16, C.c_void_p(8192 + 32), 64),   # overlapping buffers
+    (C.c_void_p(8192 + 32), P16, 64),   # overlapping the other way
+])
+def test_probe_copy_rejects(lib, src, dst, nbytes):
+    assert lib.dct_probe_copy(src, dst, nbytes, None) == codec.DCT_ERR_INVALID
+
+
+def test_probe_copy_nothing_to_do(lib):
+    assert lib.dct_probe_copy(None, None, 0, None) == codec.DCT_OK
