@@ -73,7 +73,9 @@ int dct_codec_float(const uint8_t *src, int32_t W, int32_t H, int32_t src_stride
   dct::fill_zero_kernel<<<1, 64, 0, s>>>(acc, 1);
   if (launched()) return DCT_ERR_DEVICE;
   const dct::FloatQuant fq = float_quant(qs);
-  const unsigned kgrid = static_cast<unsigned>(std::min<int64_t>((ntiles + dct::kMfmaWaves - 1) / dct::kMfmaWaves, 4096));
+  // one wave per group of kKronCodecTiles tiles, at most 4096 workgroups
+  const int64_t ngroups = (ntiles + dct::kKronCodecTiles - 1) / dct::kKronCodecTiles;
+  const unsigned kgrid = static_cast<unsigned>(std::min<int64_t>((ngroups + dct::kMfmaWaves - 1) / dct::kMfmaWaves, 4096));
   if (form == dct::kFormF32Loeffler)
     dct::loeffler_f32_kernel<true><<<grid_for(nblocks), dct::kWg, 0, s>>>(src, W, H, src_stride, bw, nblocks, nullptr,
                                                                           fq, dst, dst_stride, acc);

@@ -296,7 +296,7 @@ struct MfmaTraits<true> {
 };
 
 inline constexpr int kMfmaWaves = 4;  // waves per workgroup; each wave codes 16 blocks per step
-inline constexpr int kKronDepth = 2;  // tiles whose words a wave has in flight ahead of the one it codes
+inline constexpr int kKronCodecTiles = 2;  // tiles the codec kernel codes per wave step, sharing operand reads
 
 // Register-only layout of the matrix form.  With blocks as the N dimension,
 // the forward product is F^T = K X^T (M = coefficient, K = pixel) and the
@@ -455,51 +455,61 @@ __device__ __forceinline__ void kron_setup(OperandTable<kBf16> *inv, const Float
   }
 }
 
-// forward product of the lane's 16 pixels (four words): acc[t][r] = coefficient 16t + 4g + r
-template <bool kBf16>
-__device__ __forceinline__ void kron_forward(const OperandTable<kBf16> *tab, int lane, const uint32_t (&w)[4],
-                                             f32x4 (&acc)[4]) {
+// forward products of kN tiles, the lane's 16 pixels (four words) of each:
+// acc[n][t][r] = coefficient 16t + 4g + r of tile n.  Each operand read from LDS
+// serves the kN tiles' products.
+template <bool kBf16, int kN>
+__device__ __forceinline__ void kron_forward(const OperandTable<kBf16> *tab, int lane, const uint32_t (&w)[kN][4],
+                                             f32x4 (&acc)[kN][4]) {
   // the table is read afresh at every call (an opaque index keeps the reads in the loop)
   asm volatile("" : "+v"(lane));
   using T = MfmaTraits<kBf16>;
   typedef typename T::vec vec;
   typedef typename T::elem elem;
-  vec bx[2];
-  if constexpr (!kBf16) {
-    // FP16 of b - 128 for two bytes at once: 0x6400 | b is 1024 + b, exact with
-    // 11 significant bits, and 1024 + b - 1152 is exact too
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    const h2 off = {static_cast<_Float16>(1152.0f), static_cast<_Float16>(1152.0f)};
+  vec bx[kN][2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+  for (int n = 0; n < kN; ++n) {
+    if constexpr (!kBf16) {
+      // FP16 of b - 128 for two bytes at once: 0x6400 | b is 1024 + b, exact with
+      // 11 significant bits, and 1024 + b - 1152 is exact too
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+      const h2 off = {static_cast<_Float16>(1152.0f), static_cast<_Float16>(1152.0f)};
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const uint32_t word = w[2 * s + (h >> 1)];
-        const uint32_t sel = (h & 1) ? 0x04030402u : 0x04010400u;  // bytes 2, 3 or 0, 1 under 0x64
-        const h2 v = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, word, sel)) - off;
-        bx[s][2 * h] = v[0];
-        bx[s][2 * h + 1] = v[1];
-      }
-  } else {
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+        for (int h = 0; h < 4; ++h) {
+          const uint32_t word = w[n][2 * s + (h >> 1)];
+          const uint32_t sel = (h & 1) ? 0x04030402u : 0x04010400u;  // bytes 2, 3 or 0, 1 under 0x64
+          const h2 v = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, word, sel)) - off;
+          bx[n][s][2 * h] = v[0];
+          bx[n][s][2 * h + 1] = v[1];
+        }
+    } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t word = w[2 * s + (e >> 2)];
-        bx[s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
-      }
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t word = w[n][2 * s + (e >> 2)];
+          bx[n][s][e] = static_cast<elem>(static_cast<float>((word >> (8 * (e & 3))) & 0xffu) - 128.0f);
+        }
+    }
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    acc[t] = T::mma(tab->fa[t][0][lane], bx[0], f32x4{0.f, 0.f, 0.f, 0.f});
-    acc[t] = T::mma(tab->fa[t][1][lane], bx[1], acc[t]);
+    const vec fa0 = tab->fa[t][0][lane], fa1 = tab->fa[t][1][lane];
+#pragma unroll
+    for (int n = 0; n < kN; ++n) {
+      acc[n][t] = T::mma(fa0, bx[n][0], f32x4{0.f, 0.f, 0.f, 0.f});
+      acc[n][t] = T::mma(fa1, bx[n][1], acc[n][t]);
+    }
   }
 }
 
-// quantize, dequantize, inverse product and reconstruction: the four output words
-template <bool kBf16>
-__device__ __forceinline__ void kron_code(const OperandTable<kBf16> *inv, int lane, const f32x4 (&acc)[4],
-                                          uint32_t (&rec)[4]) {
+// quantize, dequantize, inverse product and reconstruction of kN tiles: the four
+// output words of each; each operand and quantizer read serves the kN tiles
+template <bool kBf16, int kN>
+__device__ __forceinline__ void kron_code(const OperandTable<kBf16> *inv, int lane, const f32x4 (&acc)[kN][4],
+                                          uint32_t (&rec)[kN][4]) {
   // the table is read afresh at every call: an opaque index keeps the compiler
   // from hoisting the reads out of the tile loop into registers
   asm volatile("" : "+v"(lane));
@@ -508,22 +518,28 @@ __device__ __forceinline__ void kron_code(const OperandTable<kBf16> *inv, int la
   typedef typename T::elem elem;
   const int g = lane >> 4;
   // element e = 4(t % 2) + r of inverse step t / 2
-  vec bq[2];
+  vec bq[kN][2];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const f32x4 qv = inv->qv[t][g], rq = inv->rq[t][g];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      bq[t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant_rne(acc[t][r], rq[r], qv[r]));
+    for (int n = 0; n < kN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        bq[n][t >> 1][4 * (t & 1) + r] = static_cast<elem>(fquant_rne(acc[n][t][r], rq[r], qv[r]));
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 x = T::mma(inv->ia[t][0][lane], bq[0], f32x4{128.0f, 128.0f, 128.0f, 128.0f});
-    x = T::mma(inv->ia[t][1][lane], bq[1], x);
-    uint32_t v = 0;
+    const vec ia0 = inv->ia[t][0][lane], ia1 = inv->ia[t][1][lane];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v = pack_reconstruct(x[r], r, v);
-    rec[t] = v;
+    for (int n = 0; n < kN; ++n) {
+      f32x4 x = T::mma(ia0, bq[n][0], f32x4{128.0f, 128.0f, 128.0f, 128.0f});
+      x = T::mma(ia1, bq[n][1], x);
+      uint32_t v = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v = pack_reconstruct(x[r], r, v);
+      rec[n][t] = v;
+    }
   }
 }
 
@@ -564,69 +580,82 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_kernel(const uint8_t *__
   kron_setup<kBf16, kCodec>(&inv, fq, wave, i, g);
   __syncthreads();
   uint64_t err = 0;
-  // Each wave walks its tiles with the words of the next kKronDepth tiles in
-  // flight, in a ring of kKronDepth + 1 slots that the unrolled loop rotates: no
-  // register of a load in flight is copied, which would wait for the load.  A
-  // tile's block positions are found once, when its words are loaded.
-  constexpr int kSlots = kKronDepth + 1;
+  // A wave codes kN consecutive tiles per step (the codec: two, 32 blocks, so
+  // that each operand read from LDS serves two tiles' products) and walks its
+  // steps with the words of the next kDepth steps in flight, in a ring of
+  // kDepth + 1 slots that the unrolled loop rotates: no register of a load in
+  // flight is copied, which would wait for the load.  A tile's block positions
+  // are found once, when its words are loaded.
+  constexpr int kN = kCodec ? kKronCodecTiles : 1;
+  constexpr int kDepth = kCodec ? 1 : 2;
+  constexpr int kSlots = kDepth + 1;
+  const int ngroups = (ntiles + kN - 1) / kN;
   const int step = gridDim.x * kMfmaWaves;
-  int tile = blockIdx.x * kMfmaWaves + wave;
-  uint32_t ring[kSlots][4];
-  BlockPos rpos[kSlots];
-  // The prefetch is four unconditional buffer loads per lane: the words of a block
-  // inside the image, and for every other lane the plane's first words (a load
-  // past the plane's bytes returns zero).  With no branch around the loads the
-  // compiler keeps them in flight until their tile is coded; an edge block
-  // reloads its words then, with edge replication.  The loads (cache policy 2)
-  // and the stores of whole blocks are non-temporal: every byte of the planes is
-  // read once and written once.
+  int grp = blockIdx.x * kMfmaWaves + wave;
+  uint32_t ring[kSlots][kN][4];
+  BlockPos rpos[kSlots][kN];
+  // The prefetch is four unconditional buffer loads per lane and tile: the words
+  // of a block inside the image, and for every other lane the plane's first
+  // words (a load past the plane's bytes returns zero).  With no branch around
+  // the loads the compiler keeps them in flight until their tile is coded; an
+  // edge block reloads its words then, with edge replication.  The loads (cache
+  // policy 2) and the stores of whole blocks are non-temporal: every byte of the
+  // planes is read once and written once.
   const __amdgpu_buffer_rsrc_t plane =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(src), 0,
                                         static_cast<int>(static_cast<uint32_t>(H - 1) * static_cast<uint32_t>(stride) +
                                                          static_cast<uint32_t>(W)),
                                         0x00020000);
-  auto fetch = [&](int t, uint32_t(&w)[4], BlockPos &p) {
-    p = tile_pos(t, i, W, H, bw, nblocks);
-    const uint32_t off = p.full ? static_cast<uint32_t>(p.by * 8 + (g >> 1)) * static_cast<uint32_t>(stride) +
-                                      static_cast<uint32_t>(p.bx * 8 + 4 * (g & 1))
-                                : 0u;
+  auto fetch = [&](int gi, uint32_t(&w)[kN][4], BlockPos(&p)[kN]) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      w[k] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(
-          plane, static_cast<int>(off + static_cast<uint32_t>(2 * k * stride)), 0, 2));
+    for (int n = 0; n < kN; ++n) {
+      p[n] = tile_pos(gi * kN + n, i, W, H, bw, nblocks);
+      const uint32_t off = p[n].full ? static_cast<uint32_t>(p[n].by * 8 + (g >> 1)) * static_cast<uint32_t>(stride) +
+                                           static_cast<uint32_t>(p[n].bx * 8 + 4 * (g & 1))
+                                     : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        w[n][k] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(
+            plane, static_cast<int>(off + static_cast<uint32_t>(2 * k * stride)), 0, 2));
+    }
   };
 #pragma unroll
-  for (int d = 0; d < kKronDepth; ++d) fetch(tile + d * step, ring[d], rpos[d]);
-  while (tile < ntiles) {
+  for (int d = 0; d < kDepth; ++d) fetch(grp + d * step, ring[d], rpos[d]);
+  while (grp < ngroups) {
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) {
-      if (tile < ntiles) {
-        fetch(tile + kKronDepth * step, ring[(k + kKronDepth) % kSlots], rpos[(k + kKronDepth) % kSlots]);
-        uint32_t(&w)[4] = ring[k];
-        const BlockPos &p = rpos[k];
-        if (!p.full && p.live) load_words(src, W, H, stride, p.by, p.bx, g, false, w);
-        f32x4 acc[4];
-        kron_forward<kBf16>(&inv, l, w, acc);
+      if (grp < ngroups) {
+        fetch(grp + kDepth * step, ring[(k + kDepth) % kSlots], rpos[(k + kDepth) % kSlots]);
+        uint32_t(&w)[kN][4] = ring[k];
+        const BlockPos(&p)[kN] = rpos[k];
+#pragma unroll
+        for (int n = 0; n < kN; ++n)
+          if (!p[n].full && p[n].live) load_words(src, W, H, stride, p[n].by, p[n].bx, g, false, w[n]);
+        f32x4 acc[kN][4];
+        kron_forward<kBf16, kN>(&inv, l, w, acc);
         if constexpr (!kCodec) {
-          if (p.live) {
-            const size_t b = static_cast<size_t>(tile) * 16 + i;
+          if (p[0].live) {
+            const size_t b = static_cast<size_t>(grp) * 16 + i;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
               *reinterpret_cast<float4 *>(coef + b * 64 + 16 * t + 4 * g) =
-                  make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+                  make_float4(acc[0][t][0], acc[0][t][1], acc[0][t][2], acc[0][t][3]);
           }
         } else {
-          uint32_t rec[4];
-          kron_code<kBf16>(&inv, l, acc, rec);
-          if (p.full) {
-            store_words(dst, W, H, dst_stride, p.by, p.bx, g, true, rec);
-            err += words_sse_full(w, rec);
-          } else if (p.live) {
-            store_words(dst, W, H, dst_stride, p.by, p.bx, g, false, rec);
-            err += words_sse(w, rec, W, H, p.by, p.bx, g, false);
+          uint32_t rec[kN][4];
+          kron_code<kBf16, kN>(&inv, l, acc, rec);
+#pragma unroll
+          for (int n = 0; n < kN; ++n) {
+            if (p[n].full) {
+              store_words(dst, W, H, dst_stride, p[n].by, p[n].bx, g, true, rec[n]);
+              err += words_sse_full(w[n], rec[n]);
+            } else if (p[n].live) {
+              store_words(dst, W, H, dst_stride, p[n].by, p[n].bx, g, false, rec[n]);
+              err += words_sse(w[n], rec[n], W, H, p[n].by, p[n].bx, g, false);
+            }
           }
         }
-        tile += step;
+        grp += step;
       }
     }
   }
@@ -717,15 +746,16 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
     uint32_t w[3][4] = {};
     if (p.live) load_rgb_words(rgb, W, H, rgb_stride, p.by, p.bx, g, p.full, vec_ok, w[0], w[1], w[2]);
     uint8_t *outs[3] = {out_y, out_cb, out_cr};
+    // the three planes' products share each operand read
+    f32x4 acc[3][4];
+    kron_forward<kBf16, 3>(&inv, l, w, acc);
+    uint32_t rec[3][4];
+    kron_code<kBf16, 3>(&inv, l, acc, rec);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      f32x4 acc[4];
-      kron_forward<kBf16>(&inv, l, w[c], acc);
-      uint32_t rec[4];
-      kron_code<kBf16>(&inv, l, acc, rec);
       if (p.live) {
-        store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec);
-        err[c] += words_sse(w[c], rec, W, H, p.by, p.bx, g, p.full);
+        store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec[c]);
+        err[c] += words_sse(w[c], rec[c], W, H, p.by, p.bx, g, p.full);
       }
     }
   }
