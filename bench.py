@@ -390,9 +390,22 @@ def cpu_baseline(imgs, qs, legs=True):
     out = {"value": len(imgs) * W * H / dt / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
            "sample": f"{len(imgs)} images of {W}x{H} (seeds 0-{len(imgs) - 1}), recipe codec, {cores} threads "
                      f"over block-row bands: {dt:.2f} s wall, {cpu:.1f} s CPU"}
+    out["cpu_model"] = cpu_model()
     if legs:
         out["legs"] = cpu_legs(imgs[0], qs, cores)
     return out, first[0], first[1]
+
+
+def cpu_model():
+    """The host CPU's model name (the first of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 PREC_SIZE = 2048
