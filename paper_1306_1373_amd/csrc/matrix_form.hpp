@@ -682,6 +682,23 @@ __device__ __forceinline__ void ycc_pixel(int R, int G, int B, uint32_t &y, uint
 // converted on the fly (positions as load_words).  A full block with 4-aligned
 // RGB rows reads three 4-byte words per 4 pixels; other blocks go byte by byte
 // with edge replication.
+// The Y, Cb and Cr words of four RGB pixels given as twelve bytes (R, G, B each)
+__device__ __forceinline__ void ycc_words(const uint32_t (&bytes)[12], uint32_t &y, uint32_t &cb, uint32_t &cr) {
+  uint32_t wy = 0, wb = 0, wr = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    uint32_t vy, vb, vr;
+    ycc_pixel(static_cast<int>(bytes[3 * r]), static_cast<int>(bytes[3 * r + 1]), static_cast<int>(bytes[3 * r + 2]),
+              vy, vb, vr);
+    wy |= vy << (8 * r);
+    wb |= vb << (8 * r);
+    wr |= vr << (8 * r);
+  }
+  y = wy;
+  cb = wb;
+  cr = wr;
+}
+
 __device__ __forceinline__ void load_rgb_words(const uint8_t *__restrict__ rgb, int W, int H, int rgb_stride,
                                                int by, int bx, int g, bool full, bool vec_ok, uint32_t (&y)[4],
                                                uint32_t (&cb)[4], uint32_t (&cr)[4]) {
@@ -708,19 +725,22 @@ __device__ __forceinline__ void load_rgb_words(const uint8_t *__restrict__ rgb, 
         for (int c = 0; c < 3; ++c) bytes[3 * r + c] = row[3 * xx + c];
       }
     }
-    uint32_t wy = 0, wb = 0, wr = 0;
+    ycc_words(bytes, y[t], cb[t], cr[t]);
+  }
+}
+
+// The same from the lane's twelve words of a block inside the image, loaded
+// beforehand: words 3t .. 3t + 2 hold the twelve RGB bytes of its row 2t + g/2.
+__device__ __forceinline__ void rgb_words_from_raw(const uint32_t (&raw)[12], uint32_t (&y)[4], uint32_t (&cb)[4],
+                                                   uint32_t (&cr)[4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      uint32_t vy, vb, vr;
-      ycc_pixel(static_cast<int>(bytes[3 * r]), static_cast<int>(bytes[3 * r + 1]), static_cast<int>(bytes[3 * r + 2]),
-                vy, vb, vr);
-      wy |= vy << (8 * r);
-      wb |= vb << (8 * r);
-      wr |= vr << (8 * r);
-    }
-    y[t] = wy;
-    cb[t] = wb;
-    cr[t] = wr;
+  for (int t = 0; t < 4; ++t) {
+    uint32_t bytes[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bytes[4 * k + j] = (raw[3 * t + k] >> (8 * j)) & 0xffu;
+    ycc_words(bytes, y[t], cb[t], cr[t]);
   }
 }
 
@@ -741,21 +761,60 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void kron_rgb_kernel(const uint8_t
   kron_setup<kBf16, true>(&inv, fq, wave, i, g);
   __syncthreads();
   uint64_t err[3] = {0, 0, 0};
-  for (int tile = blockIdx.x * kMfmaWaves + wave; tile < ntiles; tile += gridDim.x * kMfmaWaves) {
-    const BlockPos p = tile_pos(tile, i, W, H, bw, nblocks);
-    uint32_t w[3][4] = {};
-    if (p.live) load_rgb_words(rgb, W, H, rgb_stride, p.by, p.bx, g, p.full, vec_ok, w[0], w[1], w[2]);
-    uint8_t *outs[3] = {out_y, out_cb, out_cr};
-    // the three planes' products share each operand read
-    f32x4 acc[3][4];
-    kron_forward<kBf16, 3>(&inv, l, w, acc);
-    uint32_t rec[3][4];
-    kron_code<kBf16, 3>(&inv, l, acc, rec);
+  // The next tile's RGB words are loaded while the current tile is coded, in a
+  // ring of two slots that the unrolled loop rotates: twelve unconditional,
+  // non-temporal buffer loads per lane (a block inside the image, else the
+  // image's first words; the buffer's bounds check returns zero past its end).
+  // Edge blocks, and images whose rows are not 4-byte aligned, gather their bytes
+  // when they are coded.
+  constexpr int kSlots = 2;
+  const int step = gridDim.x * kMfmaWaves;
+  int tile = blockIdx.x * kMfmaWaves + wave;
+  uint32_t ring[kSlots][12];
+  BlockPos rpos[kSlots];
+  const __amdgpu_buffer_rsrc_t image = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(rgb), 0,
+      static_cast<int>(static_cast<uint32_t>(H - 1) * static_cast<uint32_t>(rgb_stride) + 3u * static_cast<uint32_t>(W)),
+      0x00020000);
+  auto fetch = [&](int t, uint32_t(&raw)[12], BlockPos &p) {
+    p = tile_pos(t, i, W, H, bw, nblocks);
+    const uint32_t off =
+        p.full && vec_ok ? static_cast<uint32_t>(p.by * 8 + (g >> 1)) * static_cast<uint32_t>(rgb_stride) +
+                               3u * static_cast<uint32_t>(p.bx * 8 + 4 * (g & 1))
+                         : 0u;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (p.live) {
-        store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec[c]);
-        err[c] += words_sse(w[c], rec[c], W, H, p.by, p.bx, g, p.full);
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        raw[3 * r + k] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(
+            image, static_cast<int>(off + static_cast<uint32_t>(2 * r * rgb_stride + 4 * k)), 0, 2));
+  };
+  fetch(tile, ring[0], rpos[0]);
+  uint8_t *outs[3] = {out_y, out_cb, out_cr};
+  while (tile < ntiles) {
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      if (tile < ntiles) {
+        fetch(tile + step, ring[(k + 1) % kSlots], rpos[(k + 1) % kSlots]);
+        const BlockPos &p = rpos[k];
+        uint32_t w[3][4] = {};
+        if (p.full && vec_ok)
+          rgb_words_from_raw(ring[k], w[0], w[1], w[2]);
+        else if (p.live)
+          load_rgb_words(rgb, W, H, rgb_stride, p.by, p.bx, g, p.full, vec_ok, w[0], w[1], w[2]);
+        // the three planes' products share each operand read
+        f32x4 acc[3][4];
+        kron_forward<kBf16, 3>(&inv, l, w, acc);
+        uint32_t rec[3][4];
+        kron_code<kBf16, 3>(&inv, l, acc, rec);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (p.live) {
+            store_words(outs[c], W, H, plane_stride, p.by, p.bx, g, p.full, rec[c]);
+            err[c] += words_sse(w[c], rec[c], W, H, p.by, p.bx, g, p.full);
+          }
+        }
+        tile += step;
       }
     }
   }
