@@ -106,11 +106,14 @@ inline unsigned launch_groups(int ngroups) {
   return static_cast<unsigned>(four > 8192 ? 8192 : (four < 1024 ? 1024 : four));
 }
 // LDS layout of a wave's tile: element (a, b) of block j (a the pass's output
-// index, b the line) at word 72 j + 9 a + b.  A row-pass store (fixed a, lanes
-// (j, b)) hits words 8 j + b + 9 a (mod 64) and a column-pass load (fixed b, lanes
-// (j, a)) hits 8 j + 9 a + b (mod 64): 64 different banks both ways.
+// index, b the line) at word 76 j + 9 a + b.  The LDS takes a wave's 64 accesses
+// as two halves of 32 lanes (j = 0..7, b or a = 0..3 and 4..7) over 32 banks: a
+// row-pass store (fixed a, lanes (j, b)) hits banks 12 j + b + 9 a (mod 32) and a
+// column-pass load (fixed b, lanes (j, a)) hits 12 j + 9 a + b (mod 32), 32
+// different banks in each half both ways (a 72-word block, conflict-free for 64
+// banks, collides blocks j and j + 4).
 inline constexpr int kPitch = 9;                   // LDS words per line of a block tile
-inline constexpr int kTile = 8 * kPitch;           // words per block
+inline constexpr int kTile = 76;                   // words per block
 
 // a1..a9 under recipe RC, one lane per block row; each wave codes groups of
 // eight blocks, group g = blockIdx.x * 4 + wave, g += gridDim.x * 4
