@@ -890,10 +890,11 @@ __global__ __launch_bounds__(64 * kRedWaves) void reduce_kernel(const float *__r
 //   P   rows -4 .., columns -4 .. 31 (the decoded pixels, FP16)
 //
 // Activations are stored pixel-major, 64 bytes per pixel, its four 16-byte
-// channel groups G permuted within the pixel to slot G ^ ((C >> 2) & 3) for the
-// pixel's column C in its region: the lanes that one 16-byte LDS access serves
-// read consecutive columns of one row, and their groups then fall in different
-// 16-byte bank ranges.  Since the permutation depends on the column only, a
+// channel groups G permuted within the pixel to slot G ^ ((C >> 1) & 3) for the
+// pixel's column C in its region.  The LDS serves a 16-byte access eight lanes
+// at a time over 32 four-byte banks; those lanes read eight consecutive columns
+// of one row, two pixels share each 128-byte bank row, and the permutation puts
+// the four pixels of each parity in different 16-byte bank ranges.  Since the permutation depends on the column only, a
 // lane's address for row R is its row-0 address plus R times the row pitch, a
 // constant offset of the LDS instruction.
 //
@@ -921,7 +922,7 @@ static_assert(kLdsA1 + kLdsA2 + kLdsX <= 160 * 1024, "the tile fits in one CU's 
 
 // byte offset of channel group G of the pixel with index q (row-major in its
 // region) and column C
-__device__ __forceinline__ int act_off(int q, int C, int G) { return q * 64 + 16 * (G ^ ((C >> 2) & 3)); }
+__device__ __forceinline__ int act_off(int q, int C, int G) { return q * 64 + 16 * (G ^ ((C >> 1) & 3)); }
 
 // 32 -> 32 layer on a 16-pixel x kRows tile, operands from LDS.  `src` is the
 // input region's row one above the tile's row 0 (kCin columns); rd[dx] is the
