@@ -295,7 +295,7 @@ struct MfmaTraits<true> {
   __device__ static const uint16_t *table() { return kKronBf16.v; }
 };
 
-inline constexpr int kMfmaWaves = 4;  // waves per workgroup; each wave codes 16 blocks per step
+inline constexpr int kMfmaWaves = 4;  // waves per workgroup; a tile is the 16 blocks of one product
 inline constexpr int kKronCodecTiles = 2;  // tiles the codec kernel codes per wave step, sharing operand reads
 
 // Register-only layout of the matrix form.  With blocks as the N dimension,
