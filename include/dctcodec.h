@@ -301,6 +301,11 @@ DCT_API int dct_batch_release(const void *workspace);
  *   (training != 0: for dct_deblock_forward / dct_deblock_grad; 0: for
  *   dct_deblock_apply with npix = W H); 0 if npix is out of range.
  * dct_deblock_apply: filters one decoded W x H plane into `out`.
+ * dct_deblock_apply_stack: the same for n decoded W x H images stacked
+ *   vertically in one plane (image k at rows k H .. k H + H - 1 of `decoded` and
+ *   of `out`), each filtered on its own (zeros outside it), in one launch whose
+ *   tiles run over all n images; bit for bit n dct_deblock_apply calls.  Its
+ *   workspace is dct_deblock_apply's for npix = W H.
  * dct_deblock_forward: y (float32 device array [n][h][w]) of an image set.
  * dct_deblock_grad: the gradient of the loss (float32 device array [19105],
  *   overwritten) and the loss (*loss, one double in device memory).
@@ -311,6 +316,9 @@ DCT_API int32_t dct_deblock_nparam(void);
 DCT_API size_t dct_deblock_workspace_size(int64_t npix, int32_t training);
 DCT_API int dct_deblock_apply(const uint8_t *decoded, int32_t W, int32_t H, int32_t stride, const float *params,
                               uint8_t *out, int32_t out_stride, void *workspace, size_t workspace_bytes, void *stream);
+DCT_API int dct_deblock_apply_stack(const uint8_t *decoded, int32_t W, int32_t H, int32_t n, int32_t stride,
+                                    const float *params, uint8_t *out, int32_t out_stride, void *workspace,
+                                    size_t workspace_bytes, void *stream);
 DCT_API int dct_deblock_forward(const uint8_t *decoded, int32_t plane_w, int32_t plane_h, int32_t stride,
                                 const int32_t *pos, int32_t n, int32_t h, int32_t w, const float *params, float *y,
                                 void *workspace, size_t workspace_bytes, void *stream);

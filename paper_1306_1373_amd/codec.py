@@ -66,6 +66,8 @@ _PROTOS = {
     "dct_deblock_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dct_deblock_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dct_deblock_apply_stack": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dct_deblock_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                       C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                       C.c_void_p]),
@@ -470,6 +472,23 @@ class Deblocker:
         _, ws, size = self._workspace(W * H, False)
         _check(load().dct_deblock_apply(p, W, H, s, self.params.data_ptr(), po, so, ws, size,
                                         _stream(decoded)), "dct_deblock_apply")
+        return out
+
+    def apply_stack(self, decoded, n: int, out=None):
+        """The filtered planes (uint8) of n images of equal height stacked
+        vertically in the decoded plane, in one launch."""
+        p, W, rows, s = _plane(decoded, "decoded")
+        if n < 1 or rows % n:
+            raise ValueError("the plane's rows must hold n images of equal height")
+        if out is None:
+            out = new_plane(W, rows, decoded.device)
+        po, Wo, Ho, so = _plane(out, "out")
+        if (Wo, Ho) != (W, rows):
+            raise ValueError("out shape does not match")
+        H = rows // n
+        _, ws, size = self._workspace(W * H, False)
+        _check(load().dct_deblock_apply_stack(p, W, H, int(n), s, self.params.data_ptr(), po, so, ws, size,
+                                              _stream(decoded)), "dct_deblock_apply_stack")
         return out
 
     def forward(self, decoded, pos, h: int, w: int):

@@ -65,6 +65,24 @@ int dct_deblock_apply(const uint8_t *decoded, int32_t W, int32_t H, int32_t stri
                          nullptr, nullptr, as_stream(stream));
 }
 
+int dct_deblock_apply_stack(const uint8_t *decoded, int32_t W, int32_t H, int32_t n, int32_t stride,
+                            const float *params, uint8_t *out, int32_t out_stride, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+  if (n < 1 || H < 1 || static_cast<int64_t>(n) * H > std::numeric_limits<int32_t>::max()) return DCT_ERR_INVALID;
+  const int32_t rows = n * H;
+  if (!plane_ok(decoded, W, rows, stride) || !plane_ok(out, W, rows, out_stride) || params == nullptr ||
+      !aligned(params, 4))
+    return DCT_ERR_INVALID;
+  const int64_t npix = static_cast<int64_t>(W) * rows;
+  const DeblockLayout L = deblock_layout(static_cast<int64_t>(W) * H, false);
+  if (npix >= (int64_t{1} << 31) || workspace == nullptr || !aligned(workspace, 256) || workspace_bytes < L.bytes)
+    return DCT_ERR_INVALID;
+  if (int st = check_device(nullptr)) return st;
+  dct::db::ImageSet set{decoded, nullptr, stride, W, rows, nullptr, n, H, W};
+  return deblock_forward(set, npix, params, static_cast<uint8_t *>(workspace), L, out, out_stride, nullptr,
+                         nullptr, nullptr, as_stream(stream));
+}
+
 int dct_deblock_forward(const uint8_t *decoded, int32_t plane_w, int32_t plane_h, int32_t stride, const int32_t *pos,
                         int32_t n, int32_t h, int32_t w, const float *params, float *y, void *workspace,
                         size_t workspace_bytes, void *stream) {
@@ -240,9 +258,11 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
       return DCT_ERR_DEVICE;
     auto *ops = reinterpret_cast<WeightOps *>(ws + L.ops);
     prep_ops_kernel<<<grid_for(kPrepOpsThreads), kThreads, 0, s>>>(params, ops);
-    const int64_t tiles = static_cast<int64_t>((set.w + kTW - 1) / kTW) * ((set.h + kTH - 1) / kTH);
+    // the n images of the set stacked vertically, set.h rows each
+    const int64_t tiles = static_cast<int64_t>(set.n) * ((set.w + kTW - 1) / kTW) * ((set.h + kTH - 1) / kTH);
     const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, cus));
-    fused_apply_kernel<<<grid, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, ops, out, out_stride);
+    fused_apply_kernel<<<grid, kFThreads, lds, s>>>(set.plane, set.w, set.h, set.stride, set.n, ops, out,
+                                                    out_stride);
     return launched();
   }
   prep_kernel<<<grid_for(kNParam), kThreads, 0, s>>>(params, wq, wh);

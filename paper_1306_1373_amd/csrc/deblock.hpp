@@ -999,20 +999,30 @@ __device__ __forceinline__ void store_p(_Float16 *xs, const uint32_t (&v)[kXsPer
   }
 }
 
-// The deblocked output plane of one decoded plane (W x H, pitch stride).  Each
-// workgroup takes tiles blockIdx.x, + gridDim.x, ...; the next tile's pixels
-// are fetched while this one's middle layers run, into the other of two P
-// buffers, and each layer's weights are loaded while the layer before it
-// computes.
+// The deblocked output planes of n decoded W x H images stacked vertically in
+// one plane (image k at rows k H .. k H + H - 1, pitch stride; each filtered on
+// its own, with zeros outside it).  The tiles of all images form one list:
+// each workgroup takes tiles blockIdx.x, + gridDim.x, ..., so the last round of
+// one image's tiles does not leave CUs idle when more images follow.  The next
+// tile's pixels are fetched while this one's middle layers run, into the other
+// of two P buffers, and each layer's weights are loaded while the layer before
+// it computes.
 __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *__restrict__ plane, int W, int H,
-                                                                int stride, const WeightOps *__restrict__ ops,
+                                                                int stride, int n, const WeightOps *__restrict__ ops,
                                                                 uint8_t *__restrict__ out, int out_stride) {
   extern __shared__ __align__(16) uint8_t lds[];
   uint8_t *a1 = lds;
   float *dsum = reinterpret_cast<float *>(lds);  // layer 4's per-tap sums; a1 is dead once a2 is formed
   uint8_t *a2 = lds + kLdsA1;
   _Float16 *xbuf = reinterpret_cast<_Float16 *>(lds + kLdsA1 + kLdsA2);  // two P tiles
-  const int tiles_x = (W + kTW - 1) / kTW, ntiles = tiles_x * ((H + kTH - 1) / kTH);
+  const int tiles_x = (W + kTW - 1) / kTW, per_image = tiles_x * ((H + kTH - 1) / kTH), ntiles = per_image * n;
+  // image of a tile and the tile's first row and column in that image
+  auto origin = [&](int t, int &img, int &R0, int &C0) {
+    img = t / per_image;
+    const int lt = t - img * per_image;
+    R0 = lt / tiles_x * kTH;
+    C0 = lt % tiles_x * kTW;
+  };
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l = tid & 63, i = l & 15, g = l >> 4;
@@ -1049,12 +1059,15 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
   if (tile >= ntiles) return;
   {
     uint32_t v[kXsPer];
-    fetch_p(plane, W, H, stride, tile / tiles_x * kTH, tile % tiles_x * kTW, v);
+    int img, r0, c0;
+    origin(tile, img, r0, c0);
+    fetch_p(plane + static_cast<size_t>(img) * H * stride, W, H, stride, r0, c0, v);
     store_p(xbuf, v);
   }
   __syncthreads();
   for (int cur = 0; tile < ntiles; tile += static_cast<int>(gridDim.x), cur ^= 1) {
-    const int R0 = tile / tiles_x * kTH, C0 = tile % tiles_x * kTW;
+    int img, R0, C0;
+    origin(tile, img, R0, C0);
     const _Float16 *xs = xbuf + cur * kXs;
     h8 wa2[9][2];
     f4 bv2[2];
@@ -1098,7 +1111,11 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
     // the next tile's pixels, in flight through layers 2 and 3
     const int next = tile + static_cast<int>(gridDim.x);
     uint32_t pv[kXsPer];
-    if (next < ntiles) fetch_p(plane, W, H, stride, next / tiles_x * kTH, next % tiles_x * kTW, pv);
+    if (next < ntiles) {
+      int nimg, nr0, nc0;
+      origin(next, nimg, nr0, nc0);
+      fetch_p(plane + static_cast<size_t>(nimg) * H * stride, W, H, stride, nr0, nc0, pv);
+    }
     h8 wa3[9][2];
     f4 bv3[2];
     load_mid_ops(ops, 1, wa3, bv3);
@@ -1159,7 +1176,7 @@ __global__ __launch_bounds__(kFThreads) void fused_apply_kernel(const uint8_t *_
       if (ir < H && ic < W) {
         const float y = residual(static_cast<float>(xs[(r + 4) * kCX + c + 4]), net + b4);
         const float v = fminf(fmaxf(floorf(255.0f * y + 0.5f), 0.0f), 255.0f);
-        out[static_cast<size_t>(ir) * out_stride + ic] = static_cast<uint8_t>(v);
+        out[(static_cast<size_t>(img) * H + ir) * out_stride + ic] = static_cast<uint8_t>(v);
       }
     }
     __syncthreads();

@@ -220,6 +220,14 @@ def test_deblock_abi_validation(lib):
     assert lib.dct_deblock_workspace_size(1000, 1) > lib.dct_deblock_workspace_size(1000, 0) > 0
     assert lib.dct_deblock_apply(None, 8, 8, 8, P16, P8, 8, P16, 1 << 20, None) == codec.DCT_ERR_INVALID
     assert lib.dct_deblock_apply(P8, 8, 8, 8, P16, P8, 8, P16, 16, None) == codec.DCT_ERR_INVALID  # small ws
+    assert lib.dct_deblock_apply_stack(P8, 8, 8, 0, 8, P16, P8, 8, P16, 1 << 20, None) == \
+        codec.DCT_ERR_INVALID                                                               # n = 0
+    assert lib.dct_deblock_apply_stack(P8, 8, 0, 2, 8, P16, P8, 8, P16, 1 << 20, None) == \
+        codec.DCT_ERR_INVALID                                                               # H = 0
+    assert lib.dct_deblock_apply_stack(P8, 8, 1 << 16, 1 << 16, 8, P16, P8, 8, P16, 1 << 20, None) == \
+        codec.DCT_ERR_INVALID                                                               # n H past int32
+    assert lib.dct_deblock_apply_stack(None, 8, 8, 2, 8, P16, P8, 8, P16, 1 << 20, None) == codec.DCT_ERR_INVALID
+    assert lib.dct_deblock_apply_stack(P8, 8, 8, 2, 8, P16, P8, 8, P16, 16, None) == codec.DCT_ERR_INVALID
     assert lib.dct_deblock_forward(P8, 8, 8, 8, None, 2, 4, 4, P16, P16, P16, 1 << 20, None) == \
         codec.DCT_ERR_INVALID                                                               # n > 1 needs pos
     assert lib.dct_deblock_adam(P16, P16, P16, P16, 0, 1e-3, 0.9, 0.999, 1e-8, None) == codec.DCT_ERR_INVALID

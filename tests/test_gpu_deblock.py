@@ -252,6 +252,25 @@ def test_apply_matches_oracle_1024(hip, oracle_mod):
     check_apply(hip, oracle_mod, dec, dbb.he_params(13), "1024 x 1024")
 
 
+@pytest.mark.parametrize("W,H,n", [(85, 79, 3), (29, 27, 5), (1024, 1024, 2), (1, 1, 4)])
+def test_apply_stack_equals_single_images(hip, W, H, n):
+    # n images stacked vertically in one plane, filtered in one launch: each must
+    # come out byte for byte as its own dct_deblock_apply call gives it (its own
+    # zero padding at the seams), and nothing past the stack is written
+    import torch
+    db = hip.Deblocker(dbb.he_params(31))
+    decs = [coded_pair(W, H, 40 + k, 16)[1] for k in range(n)]
+    stack = padded_plane(hip, np.concatenate(decs, axis=0))
+    pitch = (W + 7) // 8 * 8
+    buf = torch.full((n * H + 2, pitch), 0x5A, dtype=torch.uint8, device="cuda")
+    out = db.apply_stack(stack, n, out=buf[:n * H, :W]).cpu().numpy()
+    assert bool((buf[n * H:] == 0x5A).all())
+    for k in range(n):
+        one = db.apply(padded_plane(hip, decs[k])).cpu().numpy()
+        assert np.array_equal(out[k * H:(k + 1) * H], one), (W, H, n, k)
+    say(f"[gpu] deblock apply stack {n} x {W} x {H}: equal to single-image calls")
+
+
 def test_init_is_philox_box_muller(hip):
     seed = 0x1234_5678_9ABC_DEF0
     a = hip.Deblocker(seed=seed).params.cpu().numpy()
