@@ -246,7 +246,7 @@ int deblock_forward(const dct::db::ImageSet &set, int64_t npix, const float *par
   auto *g4 = reinterpret_cast<_Float16 *>(ws + L.g4);
   if (out != nullptr) {
     // inference: the operands prepared once, then workgroups that each keep a
-    // 28 x 26 output tile in LDS, one per CU, looping over the tiles
+    // 28 x 28 output tile in LDS, one per CU, looping over the tiles
     constexpr int lds = kLdsA1 + kLdsA2 + kLdsX;
     static const hipError_t attr =
         hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_apply_kernel),

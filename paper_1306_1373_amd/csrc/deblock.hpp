@@ -40,7 +40,7 @@
 //   layer4_kernel      a3 -> y (training), the loss terms and S dL/dy: the
 //                      32 -> 1 layer as one GEMM per input row with the nine
 //                      taps as its rows, then each pixel's nine tap sums added
-//   fused_apply_kernel inference in one launch: all four layers of a 28 x 26
+//   fused_apply_kernel inference in one launch: all four layers of a 28 x 28
 //                      output tile with x, a1, a2 and layer 4's tap sums in LDS
 //   bwd4_kernel        g3 from dL/dy through layer 4 and the ReLU of a3 (VALU,
 //                      one thread per pixel)
@@ -902,13 +902,14 @@ __global__ __launch_bounds__(64 * kRedWaves) void reduce_kernel(const float *__r
 // waves in turn; with an even number of waves a wave always gets
 // the same half, so its lane addresses are fixed for the whole launch.
 inline constexpr int kTW = 28;                          // output columns of a tile
-inline constexpr int kTH = 26;                          // output rows of a tile
+inline constexpr int kTH = 28;                          // output rows of a tile (3 kG3 - 2: no layer-3 row unused)
 inline constexpr int kFThreads = 512;                   // eight waves
 inline constexpr int kFWaves = kFThreads / 64;
 static_assert(kFWaves % 2 == 0, "a wave keeps its half");
 inline constexpr int kG3 = (kTH + 2 + kRows - 1) / kRows;      // a3 row groups
 inline constexpr int kG2 = (3 * kG3 + 2 + kRows - 1) / kRows;  // a2 row groups (cover a3's rows +- 1)
 inline constexpr int kR3 = 3 * kG3, kR2 = 3 * kG2, kR1 = kR2 + 2, kRX = kR1 + 2;  // rows held
+static_assert(3 * kG3 == kTH + 2, "the tile height uses every layer-3 row the tile computes");
 inline constexpr int kC2 = 34, kC1 = 34, kCX = 36;                                // columns held
 inline constexpr int kLdsA1 = kR1 * kC1 * kC * 2;       // bytes; the layer-4 sums later reuse this space
 inline constexpr int kLdsA2 = kR2 * kC2 * kC * 2;
